@@ -1,0 +1,238 @@
+/*
+ * mdx.h -- C ABI of libmdx: the data-parallel work one Dask worker does in
+ * the cuDF-merge benchmark of arXiv 2101.08878, on one MI355X (gfx950).
+ *
+ * The paper's workers shuffle both data frames on the join key and then
+ * merge what they received (Section V-B "cuDF Merge"; the RI2 cuDF figure's
+ * caption: chunk 1E8 rows, "Shuffle: True", fraction match 0.3; 3.2 GB per
+ * worker, i.e. an int64 key and an int64 payload per row).  The shuffle's
+ * local half is a hash partition of each table into P packed per-destination
+ * buffers -- the device buffers the paper's MPI4Dask layer ships with
+ * Isend/Irecv (Section IV-B, "Point-to-point Communication Coroutines", which
+ * sends raw device buffers without serialization).  The merge is an inner
+ * hash join of the partitions.  Inter-worker communication itself is not
+ * part of this library.
+ *
+ * Conventions for every entry point:
+ *  - Every function returns an int32 status (MDX_OK = 0).  No C++ exception
+ *    crosses the ABI.  On a non-OK status, mdx_last_error() returns a
+ *    thread-local message.
+ *  - All device memory is owned by the caller.  libmdx never allocates or
+ *    frees device memory; buffers whose size depends on the data are bounded
+ *    by a *_bytes() query that depends only on sizes (n, P, key type).
+ *  - Device pointers ("d_" prefix) must point to memory of the current HIP
+ *    device and be aligned to 256 bytes where they are workspaces or tables,
+ *    and to their element size otherwise.  Host pointers have an "h_" prefix.
+ *  - Work is enqueued asynchronously on the given hipStream_t (NULL = the
+ *    null stream); no call synchronizes.  Arguments are validated on the host
+ *    before anything is enqueued: a call that returns an error has enqueued
+ *    nothing.
+ *  - Keys are int32 (MDX_KEY_I32) or int64 (MDX_KEY_I64); payloads are int64.
+ *    Keys are compared as exact integers over their full range (no sentinel
+ *    value is reserved).  int32 keys are sign-extended to int64 before
+ *    hashing, so an int32 and an int64 key of equal value share a partition.
+ *  - The destination of a key is p = fmix64(key) mod P, where fmix64 is the
+ *    64-bit finalizer of MurmurHash3 applied to the key's two's-complement
+ *    bits and mod is the unsigned 64-bit remainder.  (The paper does not name
+ *    its shuffle hash; this one is fixed here.)
+ *  - Conditions only the device can see (an output larger than its
+ *    capacity, a build table whose input is not partitioned as its offsets
+ *    claim) are reported by OR-ing MDX_DEV_* bits into the caller's int32
+ *    d_status word, which the caller zeroes before the first call and reads
+ *    after synchronizing the stream.  d_status may be NULL.
+ *  - Calls that share a workspace or a table must be ordered (same stream or
+ *    explicit events); concurrent calls on different buffers are
+ *    independent.
+ */
+#ifndef MDX_H
+#define MDX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MDX_ABI_VERSION 1
+
+/* Largest number of partitions (destinations). */
+#define MDX_MAX_P 4096
+/* Largest number of rows in one table (2^34). */
+#define MDX_MAX_ROWS (INT64_C(1) << 34)
+
+/* Return statuses. */
+#define MDX_OK 0
+#define MDX_ERR_INVALID 1   /* a null pointer with n > 0, n < 0 or too large,
+                               P outside [1, MDX_MAX_P], bad key type,
+                               overlapping input/output, misaligned buffer */
+#define MDX_ERR_WORKSPACE 2 /* workspace or table smaller than its *_bytes() */
+#define MDX_ERR_HIP 3       /* a HIP runtime call or kernel launch failed */
+
+/* Key types: the value is the key width in bytes. */
+#define MDX_KEY_I32 4
+#define MDX_KEY_I64 8
+
+/* Device-side status bits OR-ed into *d_status. */
+#define MDX_DEV_OUTPUT_OVERFLOW 1 /* join output exceeded out_capacity; rows
+                                     past the capacity were not written */
+#define MDX_DEV_BAD_PARTITIONING 2 /* a row's destination did not match the
+                                      partition its offsets place it in; the
+                                      row was skipped */
+#define MDX_DEV_SCAN_TIMEOUT 4     /* internal guard: the probe's chained
+                                      scan waited too long for a predecessor
+                                      tile; output offsets are unreliable.
+                                      Never expected; reported instead of
+                                      hanging the device. */
+
+/* ABI version compiled into the library (MDX_ABI_VERSION). */
+int32_t mdx_abi_version(void);
+
+/* Static description of a status code; never NULL. */
+const char *mdx_status_string(int32_t status);
+
+/* Thread-local message about the last failing call on this thread ("" if
+ * none).  Valid until the next libmdx call on the same thread. */
+const char *mdx_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Hash partition (the local half of the shuffle).
+ *
+ * Stable partition of one table by p = fmix64(key) mod P.  On return (once
+ * the stream reaches it):
+ *   d_offsets[0] = 0, d_offsets[P] = n, and destination p's rows occupy
+ *   [d_offsets[p], d_offsets[p+1]) of d_keys_out and d_payload_out, in
+ *   their input order.  The result is unique, hence deterministic.
+ * Arguments:
+ *   d_keys [n] (key_type), d_payload [n] int64: input columns (read only).
+ *   d_keys_out [n] (key_type), d_payload_out [n] int64: outputs; must not
+ *     overlap the inputs.
+ *   d_offsets [P+1] int64: output.
+ *   d_ws: workspace of at least mdx_hash_partition_workspace_bytes(n, P,
+ *     key_type) bytes; contents on entry are ignored.
+ * n == 0 is valid (offsets all zero).  P > n is valid (empty destinations).
+ * ------------------------------------------------------------------------- */
+int32_t mdx_hash_partition_workspace_bytes(int64_t n, int32_t P, int32_t key_type,
+                                           size_t *h_bytes);
+
+int32_t mdx_hash_partition(const void *d_keys, const int64_t *d_payload, int64_t n,
+                           int32_t key_type, int32_t P, void *d_keys_out,
+                           int64_t *d_payload_out, int64_t *d_offsets, void *d_ws,
+                           size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Join build: one hash table per partition of the build (left) table.
+ *
+ * The build input is a table partitioned by mdx_hash_partition (rows of
+ * destination p in [d_offsets[p], d_offsets[p+1])).  The table memory
+ * d_table_mem (caller-owned, at least mdx_join_table_bytes(n, P, key_type)
+ * bytes) receives, per partition, an open-addressing table of the hashed keys
+ * and, where a partition holds a repeated key, the build payloads grouped by
+ * key.  The build copies d_offsets into the table, so the caller may reuse
+ * d_keys, d_payload and d_offsets afterwards; d_table_mem must stay alive and
+ * unchanged while the table is probed.
+ * *h_table is a plain struct filled on the host (no device access); it
+ * describes where things live inside d_table_mem.  There is nothing to
+ * destroy: freeing d_table_mem ends the table.
+ * A row whose destination differs from the partition its offsets place it in
+ * is skipped (not inserted) and reported with MDX_DEV_BAD_PARTITIONING.
+ * ------------------------------------------------------------------------- */
+typedef struct mdx_table {
+    int32_t abi_version; /* MDX_ABI_VERSION of the library that built it */
+    int32_t P;
+    int32_t key_type;
+    int32_t reserved;
+    int64_t n;           /* build rows */
+    void *d_mem;         /* the caller's table memory */
+    size_t bytes;        /* its size */
+    /* Internal layout inside d_mem (read-only for the caller). */
+    int64_t *d_offsets;  /* [P+1] copy of the build offsets */
+    int32_t *d_flags;    /* [P] 1 if the partition has a repeated key */
+    int64_t *d_bump;     /* [P] group allocator */
+    uint64_t *d_slots;   /* [2 * (2n + 16P)] (hash, value) slot pairs */
+    int64_t *d_gstart;   /* [2n + 16P] group start per slot */
+    int64_t *d_grouped;  /* [n] payloads grouped by key */
+} mdx_table;
+
+int32_t mdx_join_table_bytes(int64_t n_build, int32_t P, int32_t key_type, size_t *h_bytes);
+
+int32_t mdx_join_build(const void *d_keys, const int64_t *d_payload, const int64_t *d_offsets,
+                       int64_t n, int32_t P, int32_t key_type, void *d_table_mem,
+                       size_t table_bytes, mdx_table *h_table, int32_t *d_status,
+                       hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Join probe: inner equi-join of a partitioned probe (right) table against a
+ * built table, partition by partition.
+ *
+ * Output rows are (key, left payload, right payload), one per pair of equal-
+ * key rows (multiset semantics).  Partition p's output rows occupy
+ * [d_out_offsets[p], d_out_offsets[p+1]); d_out_offsets [P+1] int64 is always
+ * written and d_out_offsets[P] is the total |J|.  Within a partition the row
+ * order is implementation-defined (compare after sorting).
+ * If |J| > out_capacity, rows that would land at or past out_capacity are
+ * not written, the output contents are unspecified, and
+ * MDX_DEV_OUTPUT_OVERFLOW is set; d_out_offsets is still exact, so a caller
+ * can size the output and call again.  out_capacity == 0 with NULL output
+ * pointers computes d_out_offsets only.
+ * Arguments: d_keys [n] (the table's key type), d_payload [n], d_offsets
+ * [P+1] of the probe table; d_ws of at least mdx_join_probe_workspace_bytes(
+ * n, P, key_type) bytes; d_out_key [out_capacity] (key type), d_out_lpay and
+ * d_out_rpay [out_capacity] int64.
+ * A probe row whose destination differs from the partition its offsets place
+ * it in finds no match and is reported with MDX_DEV_BAD_PARTITIONING.
+ * ------------------------------------------------------------------------- */
+int32_t mdx_join_probe_workspace_bytes(int64_t n_probe, int32_t P, int32_t key_type,
+                                       size_t *h_bytes);
+
+int32_t mdx_join_probe(const mdx_table *h_table, const void *d_keys, const int64_t *d_payload,
+                       const int64_t *d_offsets, int64_t n, void *d_ws, size_t ws_bytes,
+                       void *d_out_key, int64_t *d_out_lpay, int64_t *d_out_rpay,
+                       int64_t out_capacity, int64_t *d_out_offsets, int32_t *d_status,
+                       hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Merge: the whole per-worker path in one call.
+ *
+ * Partitions the left (build) and right (probe) tables into P destinations,
+ * then joins every partition, processing the partitions in groups whose hash
+ * tables share one region of the workspace so that a group's tables stay in
+ * the device's last-level cache.  Output exactly as mdx_join_probe (partition
+ * p at [d_out_offsets[p], d_out_offsets[p+1]), total in d_out_offsets[P],
+ * MDX_DEV_OUTPUT_OVERFLOW if out_capacity is too small).
+ * d_ws: at least mdx_merge_workspace_bytes(nL, nR, P, key_type) bytes.
+ * group_partitions: partitions per group; 0 lets the library choose.
+ * ------------------------------------------------------------------------- */
+int32_t mdx_merge_workspace_bytes(int64_t n_left, int64_t n_right, int32_t P, int32_t key_type,
+                                  size_t *h_bytes);
+
+int32_t mdx_merge(const void *d_left_keys, const int64_t *d_left_payload, int64_t n_left,
+                  const void *d_right_keys, const int64_t *d_right_payload, int64_t n_right,
+                  int32_t key_type, int32_t P, void *d_ws, size_t ws_bytes, void *d_out_key,
+                  int64_t *d_out_lpay, int64_t *d_out_rpay, int64_t out_capacity,
+                  int64_t *d_out_offsets, int32_t *d_status, int32_t group_partitions,
+                  hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Kernel timing for benchmarks.
+ *
+ * Brackets every launch of the named kernel, made by libmdx calls on the
+ * calling thread, with hipEventRecord(h_starts[i], stream) before and
+ * hipEventRecord(h_stops[i], stream) after, on the stream the kernel is
+ * launched on, for i = *h_count; then increments *h_count.  Launches past
+ * `capacity` are not bracketed (*h_count still counts them).  The caller
+ * creates and destroys the events and keeps the arrays and the counter
+ * alive while tracing.  Up to 8 kernels can be traced at once; kernel ==
+ * NULL stops all tracing on the thread.  Names: "part_hist", "part_scatter",
+ * "tbl_init", "tbl_insert", "probe_chain", "probe_expand".
+ * ------------------------------------------------------------------------- */
+int32_t mdx_trace_kernel(const char *kernel, hipEvent_t *h_starts, hipEvent_t *h_stops,
+                         int32_t capacity, int32_t *h_count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MDX_H */

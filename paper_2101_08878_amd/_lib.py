@@ -1,0 +1,365 @@
+"""ctypes binding of libmdx (include/mdx.h).
+
+Argument marshalling only: tensors are checked for device, dtype and
+contiguity and their raw pointers are forwarded; every step of the hash
+partition and join runs in libmdx's HIP kernels.  torch supplies device
+memory (output and workspace tensors) and streams.  There is no CPU
+fallback: if libmdx.so is missing, importing this module raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmdx.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "mdx.h")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"libmdx.so not found at {LIB_PATH}; build it with `python -m paper_2101_08878_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+
+MDX_OK = 0
+MDX_ERR_INVALID = 1
+MDX_ERR_WORKSPACE = 2
+MDX_ERR_HIP = 3
+MDX_KEY_I32 = 4
+MDX_KEY_I64 = 8
+MDX_DEV_OUTPUT_OVERFLOW = 1
+MDX_DEV_BAD_PARTITIONING = 2
+MDX_DEV_SCAN_TIMEOUT = 4
+MDX_MAX_P = 4096
+
+_i32, _i64, _sz, _vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p
+
+
+class mdx_table(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", _i32), ("P", _i32), ("key_type", _i32), ("reserved", _i32),
+        ("n", _i64), ("d_mem", _vp), ("bytes", _sz),
+        ("d_offsets", _vp), ("d_flags", _vp), ("d_bump", _vp),
+        ("d_slots", _vp), ("d_gstart", _vp), ("d_grouped", _vp),
+    ]
+
+
+def _sig(name, restype, *argtypes):
+    f = getattr(_lib, name)
+    f.restype = restype
+    f.argtypes = list(argtypes)
+    return f
+
+
+_abi_version = _sig("mdx_abi_version", _i32)
+_status_string = _sig("mdx_status_string", ctypes.c_char_p, _i32)
+_last_error = _sig("mdx_last_error", ctypes.c_char_p)
+_part_ws = _sig("mdx_hash_partition_workspace_bytes", _i32, _i64, _i32, _i32, ctypes.POINTER(_sz))
+_part = _sig("mdx_hash_partition", _i32, _vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _sz, _vp)
+_table_bytes = _sig("mdx_join_table_bytes", _i32, _i64, _i32, _i32, ctypes.POINTER(_sz))
+_build = _sig("mdx_join_build", _i32, _vp, _vp, _vp, _i64, _i32, _i32, _vp, _sz,
+              ctypes.POINTER(mdx_table), _vp, _vp)
+_probe_ws = _sig("mdx_join_probe_workspace_bytes", _i32, _i64, _i32, _i32, ctypes.POINTER(_sz))
+_probe = _sig("mdx_join_probe", _i32, ctypes.POINTER(mdx_table), _vp, _vp, _vp, _i64, _vp, _sz,
+              _vp, _vp, _vp, _i64, _vp, _vp, _vp)
+_merge_ws = _sig("mdx_merge_workspace_bytes", _i32, _i64, _i64, _i32, _i32, ctypes.POINTER(_sz))
+_merge = _sig("mdx_merge", _i32, _vp, _vp, _i64, _vp, _vp, _i64, _i32, _i32, _vp, _sz,
+              _vp, _vp, _vp, _i64, _vp, _vp, _i32, _vp)
+
+_trace = _sig("mdx_trace_kernel", _i32, ctypes.c_char_p, _vp, _vp, _i32, ctypes.POINTER(_i32))
+
+ABI_FUNCTIONS = [
+    "mdx_abi_version", "mdx_status_string", "mdx_last_error",
+    "mdx_hash_partition_workspace_bytes", "mdx_hash_partition",
+    "mdx_join_table_bytes", "mdx_join_build",
+    "mdx_join_probe_workspace_bytes", "mdx_join_probe",
+    "mdx_merge_workspace_bytes", "mdx_merge",
+    "mdx_trace_kernel",
+]
+TRACEABLE_KERNELS = ["part_hist", "part_scatter", "tbl_init", "tbl_insert", "probe_chain",
+                     "probe_expand"]
+
+
+class MdxError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_status_string(status).decode()} ({status}): {message}")
+        self.status = status
+
+
+def _check(status: int):
+    if status != MDX_OK:
+        raise MdxError(status, _last_error().decode())
+
+
+def abi_version() -> int:
+    return int(_abi_version())
+
+
+def status_string(status: int) -> str:
+    return _status_string(int(status)).decode()
+
+
+def last_error() -> str:
+    return _last_error().decode()
+
+
+# ---- marshalling helpers -----------------------------------------------------
+
+def _key_type(t: torch.Tensor) -> int:
+    if t.dtype == torch.int64:
+        return MDX_KEY_I64
+    if t.dtype == torch.int32:
+        return MDX_KEY_I32
+    raise TypeError(f"keys must be int32 or int64, got {t.dtype}")
+
+
+def _dev(t: torch.Tensor, name: str, dtype=None, n=None) -> int:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a device tensor, got {t.device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if n is not None and t.numel() < n:
+        raise ValueError(f"{name} has {t.numel()} elements, needs {n}")
+    return t.data_ptr() if t.numel() else 0
+
+
+def _stream(stream) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _bytes(fn, *args) -> int:
+    out = _sz(0)
+    _check(fn(*args, ctypes.byref(out)))
+    return int(out.value)
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    # torch's caching allocator returns 512-byte aligned blocks
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+
+
+# ---- hash partition ------------------------------------------------------------
+
+def mdx_hash_partition_workspace_bytes(n: int, P: int, key_type: int = MDX_KEY_I64) -> int:
+    return _bytes(_part_ws, int(n), int(P), int(key_type))
+
+
+def mdx_hash_partition(keys: torch.Tensor, payload: torch.Tensor, P: int, *, keys_out=None,
+                       payload_out=None, offsets=None, workspace=None, stream=None):
+    """Stable partition by fmix64(key) mod P.  Returns (keys_out, payload_out,
+    offsets[P+1]) as device tensors; the work is enqueued on `stream`."""
+    n = keys.numel()
+    kt = _key_type(keys)
+    dev = keys.device
+    keys_out = torch.empty_like(keys) if keys_out is None else keys_out
+    payload_out = torch.empty(n, dtype=torch.int64, device=dev) if payload_out is None else payload_out
+    offsets = torch.empty(P + 1, dtype=torch.int64, device=dev) if offsets is None else offsets
+    need = mdx_hash_partition_workspace_bytes(n, P, kt)
+    workspace = _workspace(need, dev) if workspace is None else workspace
+    _check(_part(_dev(keys, "keys"), _dev(payload, "payload", torch.int64, n), n, kt, int(P),
+                 _dev(keys_out, "keys_out", keys.dtype, n), _dev(payload_out, "payload_out", torch.int64, n),
+                 _dev(offsets, "offsets", torch.int64, P + 1), _dev(workspace, "workspace"),
+                 workspace.numel() * workspace.element_size(), _stream(stream)))
+    return keys_out, payload_out, offsets
+
+
+# ---- join -------------------------------------------------------------------------
+
+@dataclass
+class Table:
+    """A built table: the C struct plus the tensor that owns its memory."""
+    struct: mdx_table
+    memory: torch.Tensor
+
+    @property
+    def P(self) -> int:
+        return int(self.struct.P)
+
+
+def mdx_join_table_bytes(n_build: int, P: int, key_type: int = MDX_KEY_I64) -> int:
+    return _bytes(_table_bytes, int(n_build), int(P), int(key_type))
+
+
+def mdx_join_build(keys: torch.Tensor, payload: torch.Tensor, offsets: torch.Tensor, P: int, *,
+                   table_memory=None, status=None, stream=None) -> Table:
+    n = keys.numel()
+    kt = _key_type(keys)
+    need = mdx_join_table_bytes(n, P, kt)
+    mem = _workspace(need, keys.device) if table_memory is None else table_memory
+    t = mdx_table()
+    _check(_build(_dev(keys, "keys"), _dev(payload, "payload", torch.int64, n),
+                  _dev(offsets, "offsets", torch.int64, P + 1), n, int(P), kt, _dev(mem, "table_memory"),
+                  mem.numel() * mem.element_size(), ctypes.byref(t),
+                  _dev(status, "status", torch.int32, 1) if status is not None else None,
+                  _stream(stream)))
+    return Table(t, mem)
+
+
+def mdx_join_probe_workspace_bytes(n_probe: int, P: int, key_type: int = MDX_KEY_I64) -> int:
+    return _bytes(_probe_ws, int(n_probe), int(P), int(key_type))
+
+
+def _outputs(cap: int, key_dtype, device, out):
+    if out is not None:
+        return out
+    return (torch.empty(cap, dtype=key_dtype, device=device),
+            torch.empty(cap, dtype=torch.int64, device=device),
+            torch.empty(cap, dtype=torch.int64, device=device))
+
+
+def mdx_join_probe(table: Table, keys: torch.Tensor, payload: torch.Tensor, offsets: torch.Tensor, *,
+                   out_capacity: int, out=None, out_offsets=None, workspace=None, status=None,
+                   stream=None):
+    """Probe a built table.  Returns (out_key, out_lpay, out_rpay, out_offsets).
+    Rows of partition p are at [out_offsets[p], out_offsets[p+1]); if
+    out_offsets[P] > out_capacity the rows are not all written and
+    MDX_DEV_OUTPUT_OVERFLOW is set in `status`."""
+    n = keys.numel()
+    P = table.P
+    kt = _key_type(keys)
+    dev = keys.device
+    ok, ol, orr = _outputs(out_capacity, keys.dtype, dev, out)
+    out_offsets = torch.empty(P + 1, dtype=torch.int64, device=dev) if out_offsets is None else out_offsets
+    need = mdx_join_probe_workspace_bytes(n, P, kt)
+    workspace = _workspace(need, dev) if workspace is None else workspace
+    _check(_probe(ctypes.byref(table.struct), _dev(keys, "keys"), _dev(payload, "payload", torch.int64, n),
+                  _dev(offsets, "offsets", torch.int64, P + 1), n, _dev(workspace, "workspace"),
+                  workspace.numel() * workspace.element_size(),
+                  _dev(ok, "out_key", keys.dtype, out_capacity), _dev(ol, "out_lpay", torch.int64, out_capacity),
+                  _dev(orr, "out_rpay", torch.int64, out_capacity), int(out_capacity),
+                  _dev(out_offsets, "out_offsets", torch.int64, P + 1),
+                  _dev(status, "status", torch.int32, 1) if status is not None else None,
+                  _stream(stream)))
+    return ok, ol, orr, out_offsets
+
+
+# ---- merge ---------------------------------------------------------------------------
+
+def mdx_merge_workspace_bytes(n_left: int, n_right: int, P: int, key_type: int = MDX_KEY_I64) -> int:
+    return _bytes(_merge_ws, int(n_left), int(n_right), int(P), int(key_type))
+
+
+def mdx_merge(left_keys: torch.Tensor, left_payload: torch.Tensor, right_keys: torch.Tensor,
+              right_payload: torch.Tensor, P: int, *, out_capacity: int, out=None, out_offsets=None,
+              workspace=None, status=None, group_partitions: int = 0, stream=None):
+    """Partition both tables into P destinations and join every partition.
+    Asynchronous; returns (out_key, out_lpay, out_rpay, out_offsets)."""
+    nl, nr = left_keys.numel(), right_keys.numel()
+    kt = _key_type(left_keys)
+    if right_keys.dtype != left_keys.dtype:
+        raise TypeError("left and right keys must have the same dtype")
+    dev = left_keys.device
+    ok, ol, orr = _outputs(out_capacity, left_keys.dtype, dev, out)
+    out_offsets = torch.empty(P + 1, dtype=torch.int64, device=dev) if out_offsets is None else out_offsets
+    need = mdx_merge_workspace_bytes(nl, nr, P, kt)
+    workspace = _workspace(need, dev) if workspace is None else workspace
+    _check(_merge(_dev(left_keys, "left_keys"), _dev(left_payload, "left_payload", torch.int64, nl), nl,
+                  _dev(right_keys, "right_keys"), _dev(right_payload, "right_payload", torch.int64, nr), nr,
+                  kt, int(P), _dev(workspace, "workspace"), workspace.numel() * workspace.element_size(),
+                  _dev(ok, "out_key", left_keys.dtype, out_capacity),
+                  _dev(ol, "out_lpay", torch.int64, out_capacity),
+                  _dev(orr, "out_rpay", torch.int64, out_capacity), int(out_capacity),
+                  _dev(out_offsets, "out_offsets", torch.int64, P + 1),
+                  _dev(status, "status", torch.int32, 1) if status is not None else None,
+                  int(group_partitions), _stream(stream)))
+    return ok, ol, orr, out_offsets
+
+
+def merge(left_keys, left_payload, right_keys, right_payload, P: int, *, capacity_hint=None,
+          group_partitions: int = 0, stream=None):
+    """Synchronous convenience: mdx_merge, sized by a second call when the
+    first output capacity is too small.  Returns (key, lpay, rpay,
+    out_offsets) trimmed to the result."""
+    cap = int(capacity_hint if capacity_hint is not None else max(right_keys.numel(), 1))
+    for _ in range(2):
+        status = torch.zeros(1, dtype=torch.int32, device=left_keys.device)
+        ok, ol, orr, off = mdx_merge(left_keys, left_payload, right_keys, right_payload, P,
+                                     out_capacity=cap, status=status,
+                                     group_partitions=group_partitions, stream=stream)
+        torch.cuda.synchronize(left_keys.device)
+        total = int(off[-1].item())
+        st = int(status.item())
+        if st & MDX_DEV_BAD_PARTITIONING:
+            raise MdxError(MDX_ERR_INVALID, "device reported inconsistent partitioning")
+        if total <= cap and not (st & MDX_DEV_OUTPUT_OVERFLOW):
+            return ok[:total], ol[:total], orr[:total], off
+        cap = total
+    raise MdxError(MDX_ERR_INVALID, "output capacity retry failed")
+
+
+# ---- kernel tracing (benchmarks) -------------------------------------------------------
+
+class KernelTrace:
+    """HIP event pairs around every launch of one libmdx kernel on this thread
+    (mdx_trace_kernel).  Events are created here through the HIP runtime and
+    recorded by libmdx on the stream each kernel is launched on."""
+
+    _hip = None
+
+    @classmethod
+    def _hip_lib(cls):
+        if cls._hip is None:
+            hip = ctypes.CDLL("libamdhip64.so")
+            hip.hipEventCreate.argtypes = [ctypes.POINTER(_vp)]
+            hip.hipEventCreate.restype = ctypes.c_int
+            hip.hipEventDestroy.argtypes = [_vp]
+            hip.hipEventDestroy.restype = ctypes.c_int
+            hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), _vp, _vp]
+            hip.hipEventElapsedTime.restype = ctypes.c_int
+            cls._hip = hip
+        return cls._hip
+
+    def __init__(self, kernel: str, capacity: int):
+        hip = self._hip_lib()
+        self.kernel = kernel
+        self.capacity = int(capacity)
+        self.starts = (_vp * self.capacity)()
+        self.stops = (_vp * self.capacity)()
+        for arr in (self.starts, self.stops):
+            for i in range(self.capacity):
+                ev = _vp()
+                if hip.hipEventCreate(ctypes.byref(ev)) != 0:
+                    raise RuntimeError("hipEventCreate failed")
+                arr[i] = ev
+        self.count = _i32(0)
+
+    def start(self):
+        self.count.value = 0
+        _check(_trace(self.kernel.encode(), ctypes.cast(self.starts, _vp),
+                      ctypes.cast(self.stops, _vp), self.capacity, ctypes.byref(self.count)))
+
+    @staticmethod
+    def stop_all():
+        _check(_trace(None, None, None, 0, ctypes.byref(_i32(0))))
+
+    def durations_ms(self):
+        """Per-launch durations (call after the stream has synchronized)."""
+        hip = self._hip_lib()
+        out = []
+        for i in range(min(self.count.value, self.capacity)):
+            ms = ctypes.c_float(0)
+            if hip.hipEventElapsedTime(ctypes.byref(ms), self.starts[i], self.stops[i]) != 0:
+                raise RuntimeError("hipEventElapsedTime failed")
+            out.append(float(ms.value))
+        return out
+
+    def launches(self) -> int:
+        return int(self.count.value)
+
+    def close(self):
+        hip = self._hip_lib()
+        for arr in (self.starts, self.stops):
+            for i in range(self.capacity):
+                if arr[i]:
+                    hip.hipEventDestroy(arr[i])
+                    arr[i] = None

@@ -1,0 +1,648 @@
+// Per-partition hash join (the local merge after the shuffle; arXiv
+// 2101.08878, Section V-B "cuDF Merge": each worker merges the frames it
+// received).  Inner equi-join, multiset semantics; left = build side.
+//
+// Table of partition p (see TableLayout): open addressing with linear
+// probing over 16-byte slots (hash, value), split into two halves by the top
+// bit of the hash so that each half has an empty marker no hash of that half
+// can equal.  Hashes are stored instead of keys: fmix64 is a bijection, so
+// equal hashes mean equal keys.
+//
+// Build (tbl_init, tbl_insert): every row claims a slot for its hash with a
+// compare-and-swap; the first row of a key stores its payload in the value.
+// A row that finds its hash already present marks the partition as holding
+// a repeated key.  Only such partitions then run the grouped build
+// (grp_reset, grp_count, grp_alloc, grp_scatter), which turns the value into
+// a cursor and lays the partition's payloads out grouped by key
+// ("grouped", with [gstart[s], value[s]) the group of slot s).
+//
+// Probe (probe_chain): tiles of 2048 probe rows, each inside one partition,
+// are taken in order from a ticket counter.  A tile looks up its rows,
+// counts its output rows, and obtains the number of output rows of all
+// earlier tiles from a chained scan (each tile publishes its count, then its
+// inclusive prefix; a successor sums predecessors' counts until it meets an
+// inclusive prefix).  Tiles of unique-key partitions write their matches
+// directly; tiles of repeated-key partitions record per-row prefixes and are
+// expanded by probe_expand, which spreads a tile's output over the whole
+// device in chunks (one right row can match millions of left rows).
+#include "mdx.h"
+#include "mdx_internal.hpp"
+
+namespace mdx {
+namespace {
+
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+
+constexpr uint64_t kFlagAgg = 1ull << 62;
+constexpr uint64_t kFlagIncl = 2ull << 62;
+constexpr uint64_t kValMask = (1ull << 62) - 1;
+
+__device__ __forceinline__ uint64_t empty_of_half(uint64_t t)
+{
+    return t ? 0ull : ~0ull;
+}
+
+// Slot range of partition p inside a view whose first row is o0.
+__device__ __forceinline__ void part_slots(const TView &v, int64_t o0, int p, int64_t &sb,
+                                           int64_t &H)
+{
+    const int64_t a = v.off[p], b = v.off[p + 1];
+    sb = 2 * (a - o0) + 16 * (int64_t)(p - v.pb);
+    H = b - a + 8;
+}
+
+// Partition of slot s: largest p in [pb, pe) with sb(p) <= s.
+__device__ __forceinline__ int slot_part(const TView &v, int64_t o0, int64_t s)
+{
+    int l = v.pb, h = v.pe - 1;
+    while (l < h) {
+        const int mid = (l + h + 1) >> 1;
+        if (2 * (v.off[mid] - o0) + 16 * (int64_t)(mid - v.pb) <= s)
+            l = mid;
+        else
+            h = mid - 1;
+    }
+    return l;
+}
+
+// Slot of hash h in partition (sb, H), or -1.
+__device__ __forceinline__ int64_t find_slot(const uint64_t *slots, int64_t sb, int64_t H,
+                                             uint64_t h)
+{
+    const uint64_t t = h >> 63;
+    const uint64_t empty = empty_of_half(t);
+    const int64_t base = sb + (int64_t)t * H;
+    uint64_t i = __umul64hi(h << 1, (uint64_t)H);
+    for (int64_t k = 0; k < H; ++k) {
+        const uint64_t w = slots[2 * (base + (int64_t)i)];
+        if (w == h)
+            return base + (int64_t)i;
+        if (w == empty)
+            return -1;
+        if (++i == (uint64_t)H)
+            i = 0;
+    }
+    return -1;
+}
+
+__device__ bool block_any_dup(const TView &v)
+{
+    int any = 0;
+    for (int p = v.pb + (int)threadIdx.x; p < v.pe; p += kBlock)
+        any |= v.flags[p];
+    return __syncthreads_or(any) != 0;
+}
+
+// ---- build -----------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void table_setup(const int64_t *__restrict__ off_in, int64_t n,
+                                                      int64_t *__restrict__ off_tab,
+                                                      int32_t *__restrict__ flags,
+                                                      int64_t *__restrict__ bump, int P)
+{
+    __shared__ int64_t scratch[kWavesPerBlock];
+    if (off_in)
+        sanitize_offsets(off_in, off_tab, P, n, scratch);
+    for (int p = threadIdx.x; p < P; p += kBlock) {
+        flags[p] = 0;
+        bump[p] = 0;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void tbl_init(TView v)
+{
+    const int64_t o0 = v.off[v.pb];
+    const int64_t total = 2 * (v.off[v.pe] - o0) + 16 * (int64_t)(v.pe - v.pb);
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    u64x2 *slots = (u64x2 *)v.slots;
+    for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < total; s += stride) {
+        const int p = slot_part(v, o0, s);
+        int64_t sb, H;
+        part_slots(v, o0, p, sb, H);
+        u64x2 e;
+        e.x = (s - sb < H) ? ~0ull : 0ull;
+        e.y = 0;
+        slots[s] = e;
+    }
+}
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void tbl_insert(const K *__restrict__ keys,
+                                                     const int64_t *__restrict__ pay, TView v,
+                                                     int32_t *status)
+{
+    const int64_t o0 = v.off[v.pb], o1 = v.off[v.pe];
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t r = o0 + (int64_t)blockIdx.x * kBlock + threadIdx.x; r < o1; r += stride) {
+        const uint64_t h = fmix64(key_bits(keys[r]));
+        const int p = upper_index(v.off, v.pb, v.pe, r);
+        if ((int)dest_of(h, v.d) != p) {
+            or_status(status, MDX_DEV_BAD_PARTITIONING);
+            continue;
+        }
+        int64_t sb, H;
+        part_slots(v, o0, p, sb, H);
+        const uint64_t t = h >> 63;
+        const uint64_t empty = empty_of_half(t);
+        const int64_t base = sb + (int64_t)t * H;
+        uint64_t i = __umul64hi(h << 1, (uint64_t)H);
+        // The half holds at most n_p of its H = n_p + 8 slots, so an empty
+        // slot exists and the walk ends within H steps.
+        for (int64_t k = 0; k < H; ++k) {
+            uint64_t *sp = v.slots + 2 * (base + (int64_t)i);
+            uint64_t w = __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (w == empty) {
+                uint64_t expect = empty;
+                if (__hip_atomic_compare_exchange_strong(sp, &expect, h, __ATOMIC_RELAXED,
+                                                         __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT)) {
+                    sp[1] = (uint64_t)pay[r];
+                    break;
+                }
+                w = expect;
+            }
+            if (w == h) {
+                v.flags[p] = 1;  // repeated key
+                break;
+            }
+            if (++i == (uint64_t)H)
+                i = 0;
+        }
+    }
+}
+
+// Repeated-key partitions: value := 0 on every slot.
+__global__ __launch_bounds__(kBlock) void grp_reset(TView v)
+{
+    if (!block_any_dup(v))
+        return;
+    const int64_t o0 = v.off[v.pb];
+    const int64_t total = 2 * (v.off[v.pe] - o0) + 16 * (int64_t)(v.pe - v.pb);
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < total; s += stride) {
+        if (v.flags[slot_part(v, o0, s)])
+            v.slots[2 * s + 1] = 0;
+    }
+}
+
+// Slot of row r if r belongs to a repeated-key partition of the view, else -1.
+template <typename K>
+__device__ __forceinline__ int64_t dup_row_slot(const K *keys, const TView &v, int64_t o0,
+                                                int64_t r, int64_t o1)
+{
+    if (r >= o1)
+        return -1;
+    const uint64_t h = fmix64(key_bits(keys[r]));
+    const int p = upper_index(v.off, v.pb, v.pe, r);
+    if (!v.flags[p] || (int)dest_of(h, v.d) != p)
+        return -1;
+    int64_t sb, H;
+    part_slots(v, o0, p, sb, H);
+    return find_slot(v.slots, sb, H, h);
+}
+
+// value[s] += rows of the slot's key (wave-aggregated per slot).
+template <typename K>
+__global__ __launch_bounds__(kBlock) void grp_count(const K *__restrict__ keys, TView v)
+{
+    if (!block_any_dup(v))
+        return;
+    const int64_t o0 = v.off[v.pb], o1 = v.off[v.pe];
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    const int lane = lane_id();
+    for (int64_t b = o0 + (int64_t)blockIdx.x * kBlock; b < o1; b += stride) {
+        const int64_t s = dup_row_slot(keys, v, o0, b + threadIdx.x, o1);
+        uint64_t active = ballot(s >= 0);
+        while (active) {
+            const int leader = __ffsll((unsigned long long)active) - 1;
+            const int64_t ls = __shfl(s, leader, kWave);
+            const uint64_t mask = ballot(s == ls) & active;
+            if (lane == leader)
+                atomicAdd((unsigned long long *)&v.slots[2 * ls + 1],
+                          (unsigned long long)__popcll(mask));
+            active &= ~mask;
+        }
+    }
+}
+
+// Give every key of a repeated-key partition its range of the grouped array:
+// gstart[s] = value[s] = (partition's first row) + running total.
+__global__ __launch_bounds__(kBlock) void grp_alloc(TView v)
+{
+    if (!block_any_dup(v))
+        return;
+    const int64_t o0 = v.off[v.pb];
+    const int64_t total = 2 * (v.off[v.pe] - o0) + 16 * (int64_t)(v.pe - v.pb);
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    const int lane = lane_id();
+    for (int64_t b = (int64_t)blockIdx.x * kBlock; b < total; b += stride) {
+        const int64_t s = b + threadIdx.x;
+        int p = -1;
+        int64_t c = 0;
+        if (s < total) {
+            p = slot_part(v, o0, s);
+            int64_t sb, H;
+            part_slots(v, o0, p, sb, H);
+            const uint64_t w = v.slots[2 * s];
+            const uint64_t empty = empty_of_half((s - sb) >= H ? 1 : 0);
+            if (!v.flags[p] || w == empty)
+                p = -1;
+            else
+                c = (int64_t)v.slots[2 * s + 1];
+        }
+        uint64_t active = ballot(p >= 0);
+        while (active) {
+            const int leader = __ffsll((unsigned long long)active) - 1;
+            const int lp = __shfl(p, leader, kWave);
+            const uint64_t mask = ballot(p == lp) & active;
+            const bool mine = (mask >> lane) & 1ull;
+            const int64_t incl = wave_incl_scan(mine ? c : 0, lane);
+            const int64_t sum = __shfl(incl, kWave - 1, kWave);
+            int64_t base = 0;
+            if (lane == leader)
+                base = (int64_t)atomicAdd((unsigned long long *)&v.bump[lp],
+                                          (unsigned long long)sum);
+            base = __shfl(base, leader, kWave);
+            if (mine) {
+                const int64_t start = (v.off[lp] - o0) + base + incl - c;
+                v.gstart[s] = start;
+                v.slots[2 * s + 1] = (uint64_t)start;
+            }
+            active &= ~mask;
+        }
+    }
+}
+
+// grouped[value[s]++] = payload, for every row of a repeated-key partition.
+template <typename K>
+__global__ __launch_bounds__(kBlock) void grp_scatter(const K *__restrict__ keys,
+                                                      const int64_t *__restrict__ pay, TView v)
+{
+    if (!block_any_dup(v))
+        return;
+    const int64_t o0 = v.off[v.pb], o1 = v.off[v.pe];
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    const int lane = lane_id();
+    for (int64_t b = o0 + (int64_t)blockIdx.x * kBlock; b < o1; b += stride) {
+        const int64_t r = b + threadIdx.x;
+        const int64_t s = dup_row_slot(keys, v, o0, r, o1);
+        uint64_t active = ballot(s >= 0);
+        while (active) {
+            const int leader = __ffsll((unsigned long long)active) - 1;
+            const int64_t ls = __shfl(s, leader, kWave);
+            const uint64_t mask = ballot(s == ls) & active;
+            int64_t base = 0;
+            if (lane == leader)
+                base = (int64_t)atomicAdd((unsigned long long *)&v.slots[2 * ls + 1],
+                                          (unsigned long long)__popcll(mask));
+            base = __shfl(base, leader, kWave);
+            if ((mask >> lane) & 1ull)
+                v.grouped[base + mbcnt(mask)] = pay[r];
+            active &= ~mask;
+        }
+    }
+}
+
+// ---- probe -----------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void probe_plan(const int64_t *__restrict__ offR, int64_t n,
+                                                     int P, ProbeWs w)
+{
+    __shared__ int64_t scratch[kWavesPerBlock];
+    if (blockIdx.x == 0) {
+        sanitize_offsets(offR, w.off, P, n, scratch);
+        int64_t carry = 0;
+        for (int base = 0; base < P; base += kBlock) {
+            const int p = base + threadIdx.x;
+            const int64_t nt =
+                p < P ? (w.off[p + 1] - w.off[p] + kProbeTile - 1) / kProbeTile : 0;
+            int64_t tot;
+            const int64_t ex = block_excl_scan(nt, scratch, &tot);
+            if (p < P) {
+                w.tile_start[p] = carry + ex;
+                w.ticket[p] = 0;
+            }
+            carry += tot;
+        }
+        if (threadIdx.x == 0) {
+            w.tile_start[P] = carry;
+            *w.ndefer = 0;
+        }
+    }
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < w.max_tiles; i += stride)
+        w.status[i] = 0;
+}
+
+// Chained scan step for tile `tile` with count `agg`, run by one full wave.
+// Returns the number of output rows of all earlier tiles.  Every tile that
+// was handed out publishes, so the wait below ends; as a guard it gives up
+// after kSpinLimit polls and reports MDX_DEV_SCAN_TIMEOUT.
+constexpr int64_t kSpinLimit = 1ll << 24;
+
+__device__ int64_t lookback(uint64_t *st, int64_t tile, int64_t agg, int lane, int32_t *status)
+{
+    if (tile == 0) {
+        if (lane == 0)
+            st_agent(st, kFlagIncl | (uint64_t)agg);
+        return 0;
+    }
+    if (lane == 0)
+        st_agent(st + tile, kFlagAgg | (uint64_t)agg);
+    int64_t excl = 0;
+    int64_t j = tile - 1;
+    int64_t polls = 0;
+    for (;;) {
+        const int64_t idx = j - lane;
+        const uint64_t s = idx >= 0 ? ld_agent(st + idx) : kFlagIncl;
+        const uint64_t f = s >> 62;
+        const uint64_t incl = ballot(f == 2);
+        const uint64_t zero = ballot(f == 0);
+        const int L = incl ? __ffsll((unsigned long long)incl) - 1 : kWave - 1;
+        const uint64_t upto = (L == kWave - 1) ? ~0ull : ((2ull << L) - 1);
+        if (zero & upto) {
+            if (++polls > kSpinLimit) {
+                if (lane == 0)
+                    or_status(status, MDX_DEV_SCAN_TIMEOUT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        excl += wave_sum(lane <= L ? (int64_t)(s & kValMask) : 0);
+        if (incl)
+            break;
+        j -= kWave;
+    }
+    if (lane == 0)
+        st_agent(st + tile, kFlagIncl | (uint64_t)(excl + agg));
+    return excl;
+}
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void probe_chain(const K *__restrict__ pk,
+                                                      const int64_t *__restrict__ pv, TView v,
+                                                      int group, ProbeWs w, ProbeOut o,
+                                                      int32_t *status)
+{
+    constexpr int RP = kProbeRows;
+    __shared__ int64_t s_tile, s_excl;
+    __shared__ int64_t cw[RP][kWavesPerBlock];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    const int64_t t_begin = w.tile_start[v.pb], t_end = w.tile_start[v.pe];
+    const int64_t o0 = v.off[v.pb];
+    K *out_key = (K *)o.key;
+
+    for (;;) {
+        if (tid == 0)
+            s_tile = t_begin + (int64_t)atomicAdd(&w.ticket[group], 1u);
+        __syncthreads();
+        const int64_t tile = s_tile;
+        if (tile >= t_end)
+            break;
+        const int p = upper_index(w.tile_start, v.pb, v.pe, tile);
+        const int64_t rbeg = w.off[p] + (tile - w.tile_start[p]) * kProbeTile;
+        const int64_t rlim = w.off[p + 1];
+        const int64_t rend = rbeg + kProbeTile < rlim ? rbeg + kProbeTile : rlim;
+        const bool dup = v.flags[p] != 0;
+        int64_t sb, H;
+        part_slots(v, o0, p, sb, H);
+
+        K kk[RP];
+        int64_t vv[RP], m[RP], lv[RP];
+        bool bad = false;
+#pragma unroll
+        for (int c = 0; c < RP; ++c) {
+            const int64_t r = rbeg + (int64_t)c * kBlock + tid;
+            const bool valid = r < rend;
+            kk[c] = valid ? __builtin_nontemporal_load(pk + r) : K(0);
+            vv[c] = valid ? __builtin_nontemporal_load(pv + r) : 0;
+        }
+#pragma unroll
+        for (int c = 0; c < RP; ++c) {
+            const int64_t r = rbeg + (int64_t)c * kBlock + tid;
+            m[c] = 0;
+            lv[c] = 0;
+            if (r < rend) {
+                const uint64_t h = fmix64(key_bits(kk[c]));
+                if ((int)dest_of(h, v.d) != p) {
+                    bad = true;
+                } else {
+                    const int64_t s = find_slot(v.slots, sb, H, h);
+                    if (s >= 0) {
+                        const uint64_t val = v.slots[2 * s + 1];
+                        if (!dup) {
+                            m[c] = 1;
+                            lv[c] = (int64_t)val;
+                        } else {
+                            const int64_t g0 = v.gstart[s];
+                            m[c] = (int64_t)val - g0;
+                            lv[c] = g0;
+                        }
+                    }
+                }
+            }
+        }
+        if (bad)
+            or_status(status, MDX_DEV_BAD_PARTITIONING);
+
+        // Output rank of every row: order (c, thread), i.e. row order.
+        int64_t mex[RP];
+#pragma unroll
+        for (int c = 0; c < RP; ++c) {
+            const int64_t inc = wave_incl_scan(m[c], lane);
+            mex[c] = inc - m[c];
+            if (lane == kWave - 1)
+                cw[c][wv] = inc;
+        }
+        __syncthreads();
+        int64_t run = 0, cbase[RP];
+#pragma unroll
+        for (int c = 0; c < RP; ++c) {
+#pragma unroll
+            for (int ww = 0; ww < kWavesPerBlock; ++ww) {
+                const int64_t x = cw[c][ww];
+                if (ww == wv)
+                    cbase[c] = run;
+                run += x;
+            }
+        }
+        const int64_t M = run;
+        if (wv == 0) {
+            const int64_t ex = lookback(w.status, tile, M, lane, status);
+            if (lane == 0) {
+                s_excl = ex;
+                w.tile_base[tile] = ex;
+            }
+        }
+        __syncthreads();
+        const int64_t E = s_excl;
+        if (E + M > o.cap) {
+            if (tid == 0 && M > 0)
+                or_status(status, MDX_DEV_OUTPUT_OVERFLOW);
+        } else if (!dup) {
+#pragma unroll
+            for (int c = 0; c < RP; ++c) {
+                if (m[c]) {
+                    const int64_t at = E + cbase[c] + mex[c];
+                    out_key[at] = kk[c];
+                    o.lpay[at] = lv[c];
+                    o.rpay[at] = vv[c];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < RP; ++c) {
+                const int64_t r = rbeg + (int64_t)c * kBlock + tid;
+                if (r < rend) {
+                    w.row_pre[r] = cbase[c] + mex[c];
+                    w.row_gs[r] = lv[c];
+                }
+            }
+            if (tid == 0 && M > 0) {
+                const uint32_t d = atomicAdd(w.ndefer, 1u);
+                Deferred D;
+                D.rbeg = rbeg;
+                D.rend = rend;
+                D.base = E;
+                D.count = M;
+                D.group = group;
+                w.defer[d] = D;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void probe_expand(const K *__restrict__ pk,
+                                                       const int64_t *__restrict__ pv, TView v,
+                                                       int group, ProbeWs w, ProbeOut o)
+{
+    constexpr int64_t CH = 4096;  // output rows per chunk
+    __shared__ int64_t pre[kProbeTile];
+    const uint32_t nd = *w.ndefer;
+    const int64_t G = gridDim.x;
+    K *out_key = (K *)o.key;
+    int64_t acc = 0;  // global index of the current entry's first chunk
+    for (uint32_t e = 0; e < nd; ++e) {
+        const Deferred D = w.defer[e];
+        if (D.group != group)
+            continue;
+        const int64_t nch = (D.count + CH - 1) / CH;
+        int64_t j = (((int64_t)blockIdx.x - acc) % G + G) % G;
+        if (j < nch) {
+            const int rows = (int)(D.rend - D.rbeg);
+            for (int i = threadIdx.x; i < rows; i += kBlock)
+                pre[i] = w.row_pre[D.rbeg + i];
+            __syncthreads();
+            for (; j < nch; j += G) {
+                const int64_t lim = (j + 1) * CH < D.count ? (j + 1) * CH : D.count;
+                for (int64_t q = j * CH + threadIdx.x; q < lim; q += kBlock) {
+                    int l = 0, h = rows - 1;  // last row whose prefix <= q
+                    while (l < h) {
+                        const int mid = (l + h + 1) >> 1;
+                        if (pre[mid] <= q)
+                            l = mid;
+                        else
+                            h = mid - 1;
+                    }
+                    const int64_t r = D.rbeg + l;
+                    const int64_t at = D.base + q;
+                    out_key[at] = pk[r];
+                    o.lpay[at] = v.grouped[w.row_gs[r] + (q - pre[l])];
+                    o.rpay[at] = pv[r];
+                }
+            }
+            __syncthreads();
+        }
+        acc += nch;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void probe_finalize(int P, ProbeWs w, ProbeOut o)
+{
+    const int64_t TT = w.tile_start[P];
+    const int64_t total = TT > 0 ? (int64_t)(ld_agent(w.status + TT - 1) & kValMask) : 0;
+    for (int p = threadIdx.x; p <= P; p += kBlock) {
+        const int64_t t = w.tile_start[p];
+        o.offsets[p] = t < TT ? w.tile_base[t] : total;
+    }
+}
+
+template <typename K>
+hipError_t run_build(const K *keys, const int64_t *pay, const TView &v, int32_t *status,
+                     hipStream_t s)
+{
+    const int G = device_fill_blocks();
+    trace_begin("tbl_init", s);
+    hipLaunchKernelGGL(tbl_init, dim3(G), dim3(kBlock), 0, s, v);
+    trace_end("tbl_init", s);
+    trace_begin("tbl_insert", s);
+    hipLaunchKernelGGL((tbl_insert<K>), dim3(G), dim3(kBlock), 0, s, keys, pay, v, status);
+    trace_end("tbl_insert", s);
+    hipLaunchKernelGGL(grp_reset, dim3(G), dim3(kBlock), 0, s, v);
+    hipLaunchKernelGGL((grp_count<K>), dim3(G), dim3(kBlock), 0, s, keys, v);
+    hipLaunchKernelGGL(grp_alloc, dim3(G), dim3(kBlock), 0, s, v);
+    hipLaunchKernelGGL((grp_scatter<K>), dim3(G), dim3(kBlock), 0, s, keys, pay, v);
+    return hipGetLastError();
+}
+
+template <typename K>
+hipError_t run_probe_group(const K *pk, const int64_t *pv, const TView &v, int group,
+                           const ProbeWs &w, const ProbeOut &o, int32_t *status, hipStream_t s)
+{
+    const int G = device_fill_blocks();
+    trace_begin("probe_chain", s);
+    hipLaunchKernelGGL((probe_chain<K>), dim3(G), dim3(kBlock), 0, s, pk, pv, v, group, w, o,
+                       status);
+    trace_end("probe_chain", s);
+    trace_begin("probe_expand", s);
+    hipLaunchKernelGGL((probe_expand<K>), dim3(G), dim3(kBlock), 0, s, pk, pv, v, group, w, o);
+    trace_end("probe_expand", s);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_table_setup(const int64_t *off_in, int64_t n, int64_t *off_tab, int32_t *flags,
+                              int64_t *bump, int32_t P, hipStream_t s)
+{
+    hipLaunchKernelGGL(table_setup, dim3(1), dim3(kBlock), 0, s, off_in, n, off_tab, flags, bump,
+                       P);
+    return hipGetLastError();
+}
+
+hipError_t launch_build(const void *keys, const int64_t *pay, int key_bytes, const TView &v,
+                        int32_t *status, hipStream_t s)
+{
+    if (key_bytes == 8)
+        return run_build<int64_t>((const int64_t *)keys, pay, v, status, s);
+    return run_build<int32_t>((const int32_t *)keys, pay, v, status, s);
+}
+
+hipError_t launch_probe_plan(const int64_t *offR, int64_t n, int32_t P, const ProbeWs &w,
+                             hipStream_t s)
+{
+    const int G = device_fill_blocks() / 4 > 0 ? device_fill_blocks() / 4 : 1;
+    hipLaunchKernelGGL(probe_plan, dim3(G), dim3(kBlock), 0, s, offR, n, P, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_group(const void *pkeys, const int64_t *ppay, int key_bytes, int32_t P,
+                              const TView &v, int group, const ProbeWs &w, const ProbeOut &o,
+                              int32_t *status, hipStream_t s)
+{
+    (void)P;
+    if (key_bytes == 8)
+        return run_probe_group<int64_t>((const int64_t *)pkeys, ppay, v, group, w, o, status, s);
+    return run_probe_group<int32_t>((const int32_t *)pkeys, ppay, v, group, w, o, status, s);
+}
+
+hipError_t launch_probe_finalize(int32_t P, const ProbeWs &w, const ProbeOut &o, hipStream_t s)
+{
+    hipLaunchKernelGGL(probe_finalize, dim3(1), dim3(kBlock), 0, s, P, w, o);
+    return hipGetLastError();
+}
+
+}  // namespace mdx

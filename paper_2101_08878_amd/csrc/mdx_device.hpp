@@ -1,0 +1,178 @@
+// Device helpers shared by the libmdx kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mdx {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;            // 4 waves per workgroup
+constexpr int kWavesPerBlock = kBlock / kWave;
+
+// ---- the hash -------------------------------------------------------------
+// MurmurHash3's 64-bit finalizer: xor-shift 33, multiply, xor-shift 33,
+// multiply, xor-shift 33 (all mod 2^64).  It is a bijection of uint64, so
+// two keys are equal exactly when their hashes are; the tables store hashes.
+__device__ __forceinline__ uint64_t fmix64(uint64_t x)
+{
+    x ^= x >> 33;
+    x *= 0xff51afd7ed558ccdULL;
+    x ^= x >> 33;
+    x *= 0xc4ceb9fe1a85ec53ULL;
+    x ^= x >> 33;
+    return x;
+}
+
+// Keys enter the hash as the bits of their int64 value (int32 sign-extends).
+template <typename K>
+__device__ __forceinline__ uint64_t key_bits(K k)
+{
+    return (uint64_t)(int64_t)k;
+}
+
+// Destination p = h mod P (unsigned).  Power-of-two P uses a mask.
+struct Dest {
+    uint64_t P;
+    uint64_t mask;  // P - 1 when P is a power of two
+    int32_t pow2;
+    int32_t nbits;  // bits needed to write P - 1 (0 for P = 1)
+};
+
+__device__ __forceinline__ uint32_t dest_of(uint64_t h, const Dest &d)
+{
+    return d.pow2 ? (uint32_t)(h & d.mask) : (uint32_t)(h % d.P);
+}
+
+// ---- wave primitives ------------------------------------------------------
+__device__ __forceinline__ uint64_t ballot(bool p)
+{
+    return __builtin_amdgcn_ballot_w64(p);
+}
+
+// Number of set bits of m in lanes below the calling lane.
+__device__ __forceinline__ uint32_t mbcnt(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ int lane_id()
+{
+    return (int)mbcnt(~0ull);
+}
+
+// Inclusive scan of a 64-bit value across the wave.
+__device__ __forceinline__ int64_t wave_incl_scan(int64_t v, int lane)
+{
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        int64_t u = __shfl_up(v, (unsigned)d, kWave);
+        if (lane >= d)
+            v += u;
+    }
+    return v;
+}
+
+__device__ __forceinline__ int64_t wave_sum(int64_t v)
+{
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1)
+        v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+// Exclusive scan over a 256-thread block.  Returns the thread's exclusive
+// prefix; *total receives the block sum.  Uses 4 int64 of LDS (scratch).
+__device__ __forceinline__ int64_t block_excl_scan(int64_t v, int64_t *scratch, int64_t *total)
+{
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+    int64_t inc = wave_incl_scan(v, lane);
+    if (lane == kWave - 1)
+        scratch[w] = inc;
+    __syncthreads();
+    int64_t before = 0, sum = 0;
+#pragma unroll
+    for (int i = 0; i < kWavesPerBlock; ++i) {
+        int64_t s = scratch[i];
+        before += (i < w) ? s : 0;
+        sum += s;
+    }
+    __syncthreads();
+    *total = sum;
+    return before + inc - v;
+}
+
+// Copy P+1 partition offsets, made safe to index with: out[p] =
+// min(n, max(0, in[0..p])), a non-decreasing sequence inside [0, n].
+// Offsets that were already valid are copied unchanged.  Whole block calls.
+__device__ __forceinline__ void sanitize_offsets(const int64_t *in, int64_t *out, int P, int64_t n,
+                                                 int64_t *scratch)
+{
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+    int64_t carry = 0;
+    for (int base = 0; base <= P; base += kBlock) {
+        const int p = base + tid;
+        int64_t v = p <= P ? in[p] : 0;
+        v = v < 0 ? 0 : v;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const int64_t u = __shfl_up(v, (unsigned)d, kWave);
+            if (lane >= d && u > v)
+                v = u;
+        }
+        if (lane == kWave - 1)
+            scratch[w] = v;
+        __syncthreads();
+        int64_t m = carry, all = carry;
+#pragma unroll
+        for (int i = 0; i < kWavesPerBlock; ++i) {
+            const int64_t x = scratch[i];
+            if (i < w && x > m)
+                m = x;
+            if (x > all)
+                all = x;
+        }
+        __syncthreads();
+        if (m > v)
+            v = m;
+        if (p <= P)
+            out[p] = v < n ? v : n;
+        carry = all;
+    }
+    __syncthreads();
+}
+
+// ---- device-scope atomics used by the chained scan -------------------------
+__device__ __forceinline__ uint64_t ld_agent(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void st_agent(uint64_t *p, uint64_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void or_status(int32_t *s, int32_t bits)
+{
+    if (s)
+        __hip_atomic_fetch_or(s, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Largest q in [lo, hi) with a[q] <= x, for a non-decreasing a with
+// a[lo] <= x (a has at least hi entries).
+__device__ __forceinline__ int upper_index(const int64_t *a, int lo, int hi, int64_t x)
+{
+    int l = lo, h = hi - 1;
+    while (l < h) {
+        int mid = (l + h + 1) >> 1;
+        if (a[mid] <= x)
+            l = mid;
+        else
+            h = mid - 1;
+    }
+    return l;
+}
+
+}  // namespace mdx

@@ -1,0 +1,222 @@
+// Internal host interface between the ABI layer (mdx_abi.cpp) and the kernel
+// files (partition.hip, join.hip).  Not installed; not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "mdx_device.hpp"
+
+namespace mdx {
+
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t x, size_t a = kAlign)
+{
+    return (x + a - 1) / a * a;
+}
+
+inline Dest make_dest(int32_t P)
+{
+    Dest d;
+    d.P = (uint64_t)P;
+    d.pow2 = (P & (P - 1)) == 0;
+    d.mask = d.pow2 ? (uint64_t)(P - 1) : 0;
+    int b = 0;
+    while (b < 31 && ((1u << b) < (uint32_t)P))
+        ++b;
+    d.nbits = b;
+    return d;
+}
+
+// ---- partition ------------------------------------------------------------
+// Rows per tile of the partition kernels: 256 threads x R rows.  Small P
+// keeps one tile's rows staged in LDS; large P needs LDS for its counters.
+constexpr int kPartRowsSmall = 16;   // tile 4096 rows, P <= kPartSmallMaxP
+constexpr int kPartRowsLarge = 4;    // tile 1024 rows
+constexpr int kPartSmallMaxP = 256;
+
+inline int part_rows_per_thread(int32_t P)
+{
+    return P <= kPartSmallMaxP ? kPartRowsSmall : kPartRowsLarge;
+}
+
+struct PartLayout {
+    int64_t ntiles;
+    int rows_per_thread;
+    size_t cnt_off, totals_off, bytes;
+};
+
+inline PartLayout part_layout(int64_t n, int32_t P)
+{
+    PartLayout L;
+    L.rows_per_thread = part_rows_per_thread(P);
+    const int64_t tile = (int64_t)kBlock * L.rows_per_thread;
+    L.ntiles = (n + tile - 1) / tile;
+    size_t o = 0;
+    L.cnt_off = o;
+    o += align_up((size_t)P * (size_t)L.ntiles * sizeof(int64_t));
+    L.totals_off = o;
+    o += align_up((size_t)P * sizeof(int64_t));
+    L.bytes = o;
+    return L;
+}
+
+hipError_t launch_partition(const void *keys, const int64_t *pay, int64_t n, int key_bytes,
+                            int32_t P, void *keys_out, int64_t *pay_out, int64_t *off,
+                            void *ws, hipStream_t s);
+
+// ---- join table -------------------------------------------------------------
+// Partition p of a view over partitions [pb, pe) owns slots
+//   [sb(p), sb(p) + 2 n_p + 16),  sb(p) = 2 (off[p] - off[pb]) + 16 (p - pb),
+// split into two halves of H_p = n_p + 8 slots.  A key whose hash has top
+// bit t lives in half t; half 0 marks empty slots with ~0 and half 1 with 0,
+// values no hash of that half can take, so no key value is reserved.
+struct TableLayout {
+    size_t off_off, flags_off, bump_off, slots_off, gstart_off, grouped_off, bytes;
+    int64_t nslots;
+};
+
+inline TableLayout table_layout(int64_t n, int32_t P)
+{
+    TableLayout L;
+    L.nslots = 2 * n + 16 * (int64_t)P;
+    size_t o = 0;
+    L.off_off = o;
+    o += align_up((size_t)(P + 1) * sizeof(int64_t));
+    L.flags_off = o;
+    o += align_up((size_t)P * sizeof(int32_t));
+    L.bump_off = o;
+    o += align_up((size_t)P * sizeof(int64_t));
+    L.slots_off = o;
+    o += align_up((size_t)L.nslots * 2 * sizeof(uint64_t));
+    L.gstart_off = o;
+    o += align_up((size_t)L.nslots * sizeof(int64_t));
+    L.grouped_off = o;
+    o += align_up((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    L.bytes = o;
+    return L;
+}
+
+// Device view of the tables of partitions [pb, pe).
+struct TView {
+    uint64_t *slots;
+    int64_t *gstart;
+    int64_t *grouped;
+    const int64_t *off;  // build offsets [P+1] (absolute rows)
+    int32_t *flags;      // [P]
+    int64_t *bump;       // [P]
+    int32_t pb, pe;
+    Dest d;
+};
+
+// ---- probe ------------------------------------------------------------------
+constexpr int kProbeRows = 8;                       // rows per thread
+constexpr int kProbeTile = kBlock * kProbeRows;     // 2048 rows per tile
+
+struct Deferred {
+    int64_t rbeg, rend;  // probe rows of the tile
+    int64_t base, count; // output rows [base, base + count)
+    int64_t group;
+};
+
+struct ProbeLayout {
+    int64_t max_tiles;
+    size_t off_off, tile_start_off, status_off, tile_base_off, ticket_off, ndefer_off, defer_off,
+        row_pre_off, row_gs_off, bytes;
+};
+
+inline ProbeLayout probe_layout(int64_t n, int32_t P)
+{
+    ProbeLayout L;
+    L.max_tiles = (n + kProbeTile - 1) / kProbeTile + P;
+    size_t o = 0;
+    L.off_off = o;
+    o += align_up((size_t)(P + 1) * sizeof(int64_t));
+    L.tile_start_off = o;
+    o += align_up((size_t)(P + 1) * sizeof(int64_t));
+    L.status_off = o;
+    o += align_up((size_t)L.max_tiles * sizeof(uint64_t));
+    L.tile_base_off = o;
+    o += align_up((size_t)L.max_tiles * sizeof(int64_t));
+    L.ticket_off = o;
+    o += align_up((size_t)P * sizeof(uint32_t));
+    L.ndefer_off = o;
+    o += align_up(sizeof(uint32_t));
+    L.defer_off = o;
+    o += align_up((size_t)L.max_tiles * sizeof(Deferred));
+    L.row_pre_off = o;
+    o += align_up((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    L.row_gs_off = o;
+    o += align_up((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    L.bytes = o;
+    return L;
+}
+
+struct ProbeWs {
+    int64_t *off;  // [P+1] sanitized probe offsets
+    int64_t *tile_start;
+    uint64_t *status;
+    int64_t *tile_base;
+    uint32_t *ticket;
+    uint32_t *ndefer;
+    Deferred *defer;
+    int64_t *row_pre;
+    int64_t *row_gs;
+    int64_t max_tiles;
+};
+
+inline ProbeWs probe_ws(void *base, const ProbeLayout &L)
+{
+    char *b = (char *)base;
+    ProbeWs w;
+    w.off = (int64_t *)(b + L.off_off);
+    w.tile_start = (int64_t *)(b + L.tile_start_off);
+    w.status = (uint64_t *)(b + L.status_off);
+    w.tile_base = (int64_t *)(b + L.tile_base_off);
+    w.ticket = (uint32_t *)(b + L.ticket_off);
+    w.ndefer = (uint32_t *)(b + L.ndefer_off);
+    w.defer = (Deferred *)(b + L.defer_off);
+    w.row_pre = (int64_t *)(b + L.row_pre_off);
+    w.row_gs = (int64_t *)(b + L.row_gs_off);
+    w.max_tiles = L.max_tiles;
+    return w;
+}
+
+struct ProbeOut {
+    void *key;
+    int64_t *lpay;
+    int64_t *rpay;
+    int64_t cap;
+    int64_t *offsets;  // [P+1]
+};
+
+// Number of workgroups that fill the device for grid-stride kernels.
+int device_fill_blocks();
+
+// Benchmark tracing (mdx_trace_kernel): the launch wrappers call these
+// around the launches of the kernels that can be traced.
+void trace_begin(const char *kernel, hipStream_t s);
+void trace_end(const char *kernel, hipStream_t s);
+
+// Build a view: init slots, insert rows, group repeated keys.
+hipError_t launch_build(const void *keys, const int64_t *pay, int key_bytes, const TView &v,
+                        int32_t *status, hipStream_t s);
+
+// Copy the build offsets (sanitized, for n build rows) into the table and
+// clear per-partition flags.  off_in may be null (flags only).
+hipError_t launch_table_setup(const int64_t *off_in, int64_t n, int64_t *off_tab, int32_t *flags,
+                              int64_t *bump, int32_t P, hipStream_t s);
+
+// Probe: plan tiles from the probe offsets (sanitized for n probe rows, once
+// per probe), probe one view (group g), finalize the output offsets.
+hipError_t launch_probe_plan(const int64_t *offR, int64_t n, int32_t P, const ProbeWs &w,
+                             hipStream_t s);
+hipError_t launch_probe_group(const void *pkeys, const int64_t *ppay, int key_bytes, int32_t P,
+                              const TView &v, int group, const ProbeWs &w, const ProbeOut &o,
+                              int32_t *status, hipStream_t s);
+hipError_t launch_probe_finalize(int32_t P, const ProbeWs &w, const ProbeOut &o,
+                                 hipStream_t s);
+
+}  // namespace mdx

@@ -1,0 +1,309 @@
+// Stable hash partition of one table into P packed destination buffers.
+//
+// The shuffle's local half (arXiv 2101.08878, Section V-B, cuDF merge with
+// "Shuffle: True"): each row goes to destination p = fmix64(key) mod P, and
+// destination p's rows are packed, in input order, into [off[p], off[p+1]).
+//
+// Three passes over tiles of T = 256 * R rows:
+//   part_hist       keys only: per-tile counts per destination (LDS atomics)
+//   part_scan_tiles per destination, exclusive prefix over tiles (in place)
+//   part_offsets    exclusive prefix over destinations -> off[0..P]
+//   part_scatter    keys + payloads: rank rows inside the tile with wave
+//                   ballots (one ballot per bit of p gives every lane the
+//                   mask of lanes with its destination; mbcnt of that mask is
+//                   its rank among them), stage the tile in LDS sorted by
+//                   destination, then write every destination's run with
+//                   consecutive lanes on consecutive addresses.
+// A row's output position is off[p] + (rows of p in earlier tiles) + (rows
+// of p earlier in this tile), which is the stable counting-sort position.
+#include "mdx_internal.hpp"
+
+namespace mdx {
+namespace {
+
+template <typename K, int R>
+__global__ __launch_bounds__(kBlock) void part_hist(const K *__restrict__ keys, int64_t n, Dest d,
+                                                    int64_t *__restrict__ cnt, int64_t ntiles)
+{
+    extern __shared__ uint32_t hist[];
+    const int tid = threadIdx.x;
+    const int P = (int)d.P;
+    for (int p = tid; p < P; p += kBlock)
+        hist[p] = 0;
+    const int64_t tile = blockIdx.x;
+    const int64_t row0 = tile * (int64_t)(kBlock * R);
+    K k[R];
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+        const int64_t r = row0 + (int64_t)c * kBlock + tid;
+        k[c] = r < n ? __builtin_nontemporal_load(keys + r) : K(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+        const int64_t r = row0 + (int64_t)c * kBlock + tid;
+        if (r < n)
+            atomicAdd(&hist[dest_of(fmix64(key_bits(k[c])), d)], 1u);
+    }
+    __syncthreads();
+    for (int p = tid; p < P; p += kBlock)
+        cnt[(int64_t)p * ntiles + tile] = hist[p];
+}
+
+// Block p: exclusive prefix of cnt[p][0..ntiles) in place, total to totals[p].
+__global__ __launch_bounds__(kBlock) void part_scan_tiles(int64_t *__restrict__ cnt, int64_t ntiles,
+                                                          int64_t *__restrict__ totals)
+{
+    __shared__ int64_t scratch[kWavesPerBlock];
+    constexpr int V = 8;
+    int64_t *row = cnt + (int64_t)blockIdx.x * ntiles;
+    int64_t carry = 0;
+    for (int64_t base = 0; base < ntiles; base += (int64_t)kBlock * V) {
+        const int64_t i0 = base + (int64_t)threadIdx.x * V;
+        int64_t v[V];
+        int64_t s = 0;
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            v[j] = (i0 + j < ntiles) ? row[i0 + j] : 0;
+            s += v[j];
+        }
+        int64_t tot;
+        int64_t run = carry + block_excl_scan(s, scratch, &tot);
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            if (i0 + j < ntiles)
+                row[i0 + j] = run;
+            run += v[j];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0)
+        totals[blockIdx.x] = carry;
+}
+
+__global__ __launch_bounds__(kBlock) void part_offsets(const int64_t *__restrict__ totals, int P,
+                                                       int64_t *__restrict__ off)
+{
+    __shared__ int64_t scratch[kWavesPerBlock];
+    int64_t carry = 0;
+    for (int base = 0; base < P; base += kBlock) {
+        const int p = base + threadIdx.x;
+        const int64_t v = p < P ? totals[p] : 0;
+        int64_t tot;
+        const int64_t ex = block_excl_scan(v, scratch, &tot);
+        if (p < P)
+            off[p] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0)
+        off[P] = carry;
+}
+
+// LDS carve-up of part_scatter (bytes, 16-byte aligned pieces).
+struct ScatterLds {
+    size_t stage_v, stage_k, stage_p, whist, tstart, gbase, scratch, total;
+};
+
+__host__ __device__ inline size_t al16(size_t x)
+{
+    return (x + 15) & ~(size_t)15;
+}
+
+__host__ __device__ inline ScatterLds scatter_lds(int T, int P, int key_bytes)
+{
+    ScatterLds L;
+    size_t o = 0;
+    L.stage_v = o;
+    o = al16(o + (size_t)T * 8);
+    L.stage_k = o;
+    o = al16(o + (size_t)T * key_bytes);
+    L.stage_p = o;
+    o = al16(o + (size_t)T * 2);
+    L.whist = o;
+    o = al16(o + (size_t)kWavesPerBlock * P * 4);
+    L.tstart = o;
+    o = al16(o + (size_t)P * 4);
+    L.gbase = o;
+    o = al16(o + (size_t)P * 8);
+    L.scratch = o;
+    o = al16(o + (size_t)kWavesPerBlock * 8);
+    L.total = o;
+    return L;
+}
+
+// Exclusive prefix over a[0..P) in LDS, in place (all threads call).
+__device__ inline void lds_excl_scan_u32(uint32_t *a, int P, int64_t *scratch)
+{
+    int64_t carry = 0;
+    for (int base = 0; base < P; base += kBlock) {
+        const int p = base + threadIdx.x;
+        const int64_t v = p < P ? a[p] : 0;
+        int64_t tot;
+        const int64_t ex = block_excl_scan(v, scratch, &tot);
+        if (p < P)
+            a[p] = (uint32_t)(carry + ex);
+        carry += tot;
+    }
+    __syncthreads();
+}
+
+template <typename K, int R>
+__global__ __launch_bounds__(kBlock) void part_scatter(
+    const K *__restrict__ keys, const int64_t *__restrict__ pay, int64_t n, Dest d,
+    const int64_t *__restrict__ off, const int64_t *__restrict__ pre, int64_t ntiles,
+    K *__restrict__ keys_out, int64_t *__restrict__ pay_out)
+{
+    constexpr int T = kBlock * R;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int P = (int)d.P;
+    const ScatterLds L = scatter_lds(T, P, (int)sizeof(K));
+    int64_t *stage_v = (int64_t *)(smem + L.stage_v);
+    K *stage_k = (K *)(smem + L.stage_k);
+    uint16_t *stage_p = (uint16_t *)(smem + L.stage_p);
+    uint32_t *whist = (uint32_t *)(smem + L.whist);
+    uint32_t *tstart = (uint32_t *)(smem + L.tstart);
+    int64_t *gbase = (int64_t *)(smem + L.gbase);
+    int64_t *scratch = (int64_t *)(smem + L.scratch);
+
+    const int tid = threadIdx.x, w = tid / kWave, lane = tid & (kWave - 1);
+    const int64_t tile = blockIdx.x;
+    const int64_t row0 = tile * (int64_t)T;
+
+    for (int i = tid; i < kWavesPerBlock * P; i += kBlock)
+        whist[i] = 0;
+    for (int p = tid; p < P; p += kBlock)
+        gbase[p] = off[p] + pre[(int64_t)p * ntiles + tile];
+
+    // Wave w owns the contiguous rows [wrow0, wrow0 + 64 R) of the tile;
+    // step c reads 64 consecutive rows.
+    const int64_t wrow0 = row0 + (int64_t)w * kWave * R;
+    K kr[R];
+    int64_t vr[R];
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+        const int64_t r = wrow0 + (int64_t)c * kWave + lane;
+        const bool valid = r < n;
+        kr[c] = valid ? __builtin_nontemporal_load(keys + r) : K(0);
+        vr[c] = valid ? __builtin_nontemporal_load(pay + r) : 0;
+    }
+    __syncthreads();
+
+    // Rank every row among the earlier rows of its wave with its destination.
+    uint32_t *wh = whist + w * P;
+    uint32_t pr[R], rk[R];
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+        const int64_t r = wrow0 + (int64_t)c * kWave + lane;
+        const bool valid = r < n;
+        const uint32_t p = valid ? dest_of(fmix64(key_bits(kr[c])), d) : 0u;
+        uint64_t m = ballot(valid);
+        for (int b = 0; b < d.nbits; ++b) {
+            const bool bit = (p >> b) & 1u;
+            const uint64_t bb = ballot(bit);
+            m &= bit ? bb : ~bb;
+        }
+        const uint32_t rank = mbcnt(m);
+        uint32_t prev = 0;
+        if (valid)
+            prev = wh[p];
+        if (valid && rank == 0)
+            wh[p] = prev + (uint32_t)__popcll(m);
+        pr[c] = valid ? p : 0xffffffffu;
+        rk[c] = prev + rank;
+    }
+    __syncthreads();
+
+    // Per destination: tile count, and every wave's offset inside it.
+    for (int p = tid; p < P; p += kBlock) {
+        uint32_t acc = 0;
+#pragma unroll
+        for (int ww = 0; ww < kWavesPerBlock; ++ww) {
+            const uint32_t c = whist[ww * P + p];
+            whist[ww * P + p] = acc;
+            acc += c;
+        }
+        tstart[p] = acc;
+    }
+    __syncthreads();
+    lds_excl_scan_u32(tstart, P, scratch);  // tstart[p]: first staged row of p
+    for (int p = tid; p < P; p += kBlock) {
+        const uint32_t t0 = tstart[p];
+#pragma unroll
+        for (int ww = 0; ww < kWavesPerBlock; ++ww)
+            whist[ww * P + p] += t0;
+    }
+    __syncthreads();
+
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+        if (pr[c] != 0xffffffffu) {
+            const uint32_t s = wh[pr[c]] + rk[c];
+            stage_k[s] = kr[c];
+            stage_v[s] = vr[c];
+            stage_p[s] = (uint16_t)pr[c];
+        }
+    }
+    __syncthreads();
+
+    const int rows = (int)((n - row0) < (int64_t)T ? (n - row0) : (int64_t)T);
+    for (int s = tid; s < rows; s += kBlock) {
+        const uint32_t p = stage_p[s];
+        const int64_t dst = gbase[p] + (s - (int)tstart[p]);
+        __builtin_nontemporal_store(stage_k[s], keys_out + dst);
+        __builtin_nontemporal_store(stage_v[s], pay_out + dst);
+    }
+}
+
+template <typename K, int R>
+hipError_t run_partition(const K *keys, const int64_t *pay, int64_t n, int32_t P, K *keys_out,
+                         int64_t *pay_out, int64_t *off, void *ws, hipStream_t s)
+{
+    const PartLayout L = part_layout(n, P);
+    const Dest d = make_dest(P);
+    int64_t *cnt = (int64_t *)((char *)ws + L.cnt_off);
+    int64_t *totals = (int64_t *)((char *)ws + L.totals_off);
+    if (L.ntiles > 0) {
+        trace_begin("part_hist", s);
+        hipLaunchKernelGGL((part_hist<K, R>), dim3((unsigned)L.ntiles), dim3(kBlock),
+                           (size_t)P * sizeof(uint32_t), s, keys, n, d, cnt, L.ntiles);
+        trace_end("part_hist", s);
+    }
+    hipLaunchKernelGGL(part_scan_tiles, dim3((unsigned)P), dim3(kBlock), 0, s, cnt, L.ntiles,
+                       totals);
+    hipLaunchKernelGGL(part_offsets, dim3(1), dim3(kBlock), 0, s, totals, P, off);
+    if (L.ntiles > 0) {
+        const size_t lds = scatter_lds(kBlock * R, P, (int)sizeof(K)).total;
+        hipError_t e = hipFuncSetAttribute((const void *)part_scatter<K, R>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess)
+            return e;
+        trace_begin("part_scatter", s);
+        hipLaunchKernelGGL((part_scatter<K, R>), dim3((unsigned)L.ntiles), dim3(kBlock), lds, s,
+                           keys, pay, n, d, off, cnt, L.ntiles, keys_out, pay_out);
+        trace_end("part_scatter", s);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_partition(const void *keys, const int64_t *pay, int64_t n, int key_bytes,
+                            int32_t P, void *keys_out, int64_t *pay_out, int64_t *off, void *ws,
+                            hipStream_t s)
+{
+    const int R = part_rows_per_thread(P);
+    if (key_bytes == 8) {
+        if (R == kPartRowsSmall)
+            return run_partition<int64_t, kPartRowsSmall>((const int64_t *)keys, pay, n, P,
+                                                          (int64_t *)keys_out, pay_out, off, ws, s);
+        return run_partition<int64_t, kPartRowsLarge>((const int64_t *)keys, pay, n, P,
+                                                      (int64_t *)keys_out, pay_out, off, ws, s);
+    }
+    if (R == kPartRowsSmall)
+        return run_partition<int32_t, kPartRowsSmall>((const int32_t *)keys, pay, n, P,
+                                                      (int32_t *)keys_out, pay_out, off, ws, s);
+    return run_partition<int32_t, kPartRowsLarge>((const int32_t *)keys, pay, n, P,
+                                                  (int32_t *)keys_out, pay_out, off, ws, s);
+}
+
+}  // namespace mdx
