@@ -7,7 +7,7 @@ payload per row, keys of the left table a permutation of [0, 1E8), 30% of the
 right rows matching), then hash-join every partition.  Inputs are resident in
 device memory before the timed region.  Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--group G] [--cpu-baseline off]
+    python bench.py [--steps K] [--warmup W] [--cpu-baseline off]
 """
 
 from __future__ import annotations
@@ -36,7 +36,6 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="paper", choices=["paper", "plain"])
-    ap.add_argument("--group", type=int, default=0, help="partitions per join group (0 = auto)")
     ap.add_argument("--cpu-baseline", default="on", choices=["on", "off"])
     ap.add_argument("--cpu-sample-scale", type=float, default=0.2,
                     help="fraction of the workload the oracle runs on the host")
@@ -60,6 +59,10 @@ def algorithmic_bytes_per_step(kernel, nl, nr, key_bytes, total_out):
     row = key_bytes + 8
     if kernel == "part_scatter":
         return (nl + nr) * 2 * row
+    if kernel == "rj_join":
+        # build: read a left row, write it to the table; probe: read a right
+        # row and one table entry; output rows
+        return nl * (row + 16) + nr * (row + 16) + total_out * (key_bytes + 16)
     if kernel == "tbl_insert":
         return nl * (row + 16)
     if kernel == "probe_chain":
@@ -127,7 +130,7 @@ def main():
 
     def step():
         mdx.mdx_merge(lk, lv, rk, rv, P, out_capacity=cap, out=out, out_offsets=off, workspace=ws,
-                      status=status, group_partitions=args.group, stream=stream)
+                      status=status, stream=stream)
 
     log(f"warmup {args.warmup}")
     for _ in range(args.warmup):
@@ -143,7 +146,7 @@ def main():
 
     # Breakdown pass (not the timed region): every traceable kernel bracketed
     # by events, to find the dominant one.
-    per_step_launches = 2 + 6 * P
+    per_step_launches = 4 + 6 * P
     prof_steps = 2
     traces = {k: mdx.KernelTrace(k, prof_steps * per_step_launches) for k in mdx.TRACEABLE_KERNELS}
     for t in traces.values():
@@ -193,8 +196,8 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "bytes_per_launch": int(bytes_per_launch),
                 "avg_launch_us": round(kd["avg_launch_ms"] * 1e3, 2)}
-    step_bytes = sum(algorithmic_bytes_per_step(k, nl, nr, key_bytes, total)
-                     for k in ("part_scatter", "tbl_insert", "probe_chain"))
+    step_bytes = (nl + nr) * 2 * (key_bytes + 8) + (nl + nr) * (key_bytes + 8 + 16) \
+        + total * (key_bytes + 16)
     line = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -210,8 +213,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.config}: one worker's partition+join share, "
                                f"{nl} x {nr} rows, int{8 * key_bytes} key + int64 payload, P={P}",
-                   "n_left": nl, "n_right": nr, "P": P, "output_rows": total,
-                   "group_partitions": args.group},
+                   "n_left": nl, "n_right": nr, "P": P, "output_rows": total},
         "roofline": roofline,
         "step_hbm_fraction": round(step_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in kernels.items()},

@@ -197,13 +197,17 @@ int32_t mdx_join_probe(const mdx_table *h_table, const void *d_keys, const int64
  * Merge: the whole per-worker path in one call.
  *
  * Partitions the left (build) and right (probe) tables into P destinations,
- * then joins every partition, processing the partitions in groups whose hash
- * tables share one region of the workspace so that a group's tables stay in
- * the device's last-level cache.  Output exactly as mdx_join_probe (partition
- * p at [d_out_offsets[p], d_out_offsets[p+1]), total in d_out_offsets[P],
- * MDX_DEV_OUTPUT_OVERFLOW if out_capacity is too small).
+ * then joins every partition.  Inside the workspace each destination's rows
+ * are further split by the top bits of the hash into sub-buckets small
+ * enough for one workgroup's LDS, and every sub-bucket is joined in LDS
+ * (a radix join).  If a build sub-bucket is too large for LDS (heavily
+ * repeated keys), the device switches to the global-table join of
+ * mdx_join_build/mdx_join_probe instead; no host synchronization is needed
+ * for that choice.  Output exactly as mdx_join_probe (partition p at
+ * [d_out_offsets[p], d_out_offsets[p+1]), total in d_out_offsets[P],
+ * MDX_DEV_OUTPUT_OVERFLOW if out_capacity is too small; row order inside a
+ * partition is implementation-defined).
  * d_ws: at least mdx_merge_workspace_bytes(nL, nR, P, key_type) bytes.
- * group_partitions: partitions per group; 0 lets the library choose.
  * ------------------------------------------------------------------------- */
 int32_t mdx_merge_workspace_bytes(int64_t n_left, int64_t n_right, int32_t P, int32_t key_type,
                                   size_t *h_bytes);
@@ -212,8 +216,7 @@ int32_t mdx_merge(const void *d_left_keys, const int64_t *d_left_payload, int64_
                   const void *d_right_keys, const int64_t *d_right_payload, int64_t n_right,
                   int32_t key_type, int32_t P, void *d_ws, size_t ws_bytes, void *d_out_key,
                   int64_t *d_out_lpay, int64_t *d_out_rpay, int64_t out_capacity,
-                  int64_t *d_out_offsets, int32_t *d_status, int32_t group_partitions,
-                  hipStream_t stream);
+                  int64_t *d_out_offsets, int32_t *d_status, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Kernel timing for benchmarks.
@@ -226,7 +229,8 @@ int32_t mdx_merge(const void *d_left_keys, const int64_t *d_left_payload, int64_
  * creates and destroys the events and keeps the arrays and the counter
  * alive while tracing.  Up to 8 kernels can be traced at once; kernel ==
  * NULL stops all tracing on the thread.  Names: "part_hist", "part_scatter",
- * "tbl_init", "tbl_insert", "probe_chain", "probe_expand".
+ * "seg_scatter", "rj_join", "tbl_init", "tbl_insert", "probe_chain",
+ * "probe_expand".
  * ------------------------------------------------------------------------- */
 int32_t mdx_trace_kernel(const char *kernel, hipEvent_t *h_starts, hipEvent_t *h_stops,
                          int32_t capacity, int32_t *h_count);

@@ -69,7 +69,7 @@ _probe = _sig("mdx_join_probe", _i32, ctypes.POINTER(mdx_table), _vp, _vp, _vp, 
               _vp, _vp, _vp, _i64, _vp, _vp, _vp)
 _merge_ws = _sig("mdx_merge_workspace_bytes", _i32, _i64, _i64, _i32, _i32, ctypes.POINTER(_sz))
 _merge = _sig("mdx_merge", _i32, _vp, _vp, _i64, _vp, _vp, _i64, _i32, _i32, _vp, _sz,
-              _vp, _vp, _vp, _i64, _vp, _vp, _i32, _vp)
+              _vp, _vp, _vp, _i64, _vp, _vp, _vp)
 
 _trace = _sig("mdx_trace_kernel", _i32, ctypes.c_char_p, _vp, _vp, _i32, ctypes.POINTER(_i32))
 
@@ -81,8 +81,8 @@ ABI_FUNCTIONS = [
     "mdx_merge_workspace_bytes", "mdx_merge",
     "mdx_trace_kernel",
 ]
-TRACEABLE_KERNELS = ["part_hist", "part_scatter", "tbl_init", "tbl_insert", "probe_chain",
-                     "probe_expand"]
+TRACEABLE_KERNELS = ["part_hist", "part_scatter", "seg_scatter", "rj_join", "tbl_init",
+                     "tbl_insert", "probe_chain", "probe_expand"]
 
 
 class MdxError(RuntimeError):
@@ -251,7 +251,7 @@ def mdx_merge_workspace_bytes(n_left: int, n_right: int, P: int, key_type: int =
 
 def mdx_merge(left_keys: torch.Tensor, left_payload: torch.Tensor, right_keys: torch.Tensor,
               right_payload: torch.Tensor, P: int, *, out_capacity: int, out=None, out_offsets=None,
-              workspace=None, status=None, group_partitions: int = 0, stream=None):
+              workspace=None, status=None, stream=None):
     """Partition both tables into P destinations and join every partition.
     Asynchronous; returns (out_key, out_lpay, out_rpay, out_offsets)."""
     nl, nr = left_keys.numel(), right_keys.numel()
@@ -271,12 +271,12 @@ def mdx_merge(left_keys: torch.Tensor, left_payload: torch.Tensor, right_keys: t
                   _dev(orr, "out_rpay", torch.int64, out_capacity), int(out_capacity),
                   _dev(out_offsets, "out_offsets", torch.int64, P + 1),
                   _dev(status, "status", torch.int32, 1) if status is not None else None,
-                  int(group_partitions), _stream(stream)))
+                  _stream(stream)))
     return ok, ol, orr, out_offsets
 
 
 def merge(left_keys, left_payload, right_keys, right_payload, P: int, *, capacity_hint=None,
-          group_partitions: int = 0, stream=None):
+          stream=None):
     """Synchronous convenience: mdx_merge, sized by a second call when the
     first output capacity is too small.  Returns (key, lpay, rpay,
     out_offsets) trimmed to the result."""
@@ -284,13 +284,12 @@ def merge(left_keys, left_payload, right_keys, right_payload, P: int, *, capacit
     for _ in range(2):
         status = torch.zeros(1, dtype=torch.int32, device=left_keys.device)
         ok, ol, orr, off = mdx_merge(left_keys, left_payload, right_keys, right_payload, P,
-                                     out_capacity=cap, status=status,
-                                     group_partitions=group_partitions, stream=stream)
+                                     out_capacity=cap, status=status, stream=stream)
         torch.cuda.synchronize(left_keys.device)
         total = int(off[-1].item())
         st = int(status.item())
-        if st & MDX_DEV_BAD_PARTITIONING:
-            raise MdxError(MDX_ERR_INVALID, "device reported inconsistent partitioning")
+        if st & (MDX_DEV_BAD_PARTITIONING | MDX_DEV_SCAN_TIMEOUT):
+            raise MdxError(MDX_ERR_INVALID, f"device reported status {st}")
         if total <= cap and not (st & MDX_DEV_OUTPUT_OVERFLOW):
             return ok[:total], ol[:total], orr[:total], off
         cap = total

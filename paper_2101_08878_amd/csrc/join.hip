@@ -33,10 +33,6 @@ namespace {
 
 typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
 
-constexpr uint64_t kFlagAgg = 1ull << 62;
-constexpr uint64_t kFlagIncl = 2ull << 62;
-constexpr uint64_t kValMask = (1ull << 62) - 1;
-
 __device__ __forceinline__ uint64_t empty_of_half(uint64_t t)
 {
     return t ? 0ull : ~0ull;
@@ -85,6 +81,11 @@ __device__ __forceinline__ int64_t find_slot(const uint64_t *slots, int64_t sb, 
     return -1;
 }
 
+__device__ __forceinline__ bool skipped(const int32_t *skip)
+{
+    return skip && *skip != 0;
+}
+
 __device__ bool block_any_dup(const TView &v)
 {
     int any = 0;
@@ -111,6 +112,8 @@ __global__ __launch_bounds__(kBlock) void table_setup(const int64_t *__restrict_
 
 __global__ __launch_bounds__(kBlock) void tbl_init(TView v)
 {
+    if (skipped(v.skip))
+        return;
     const int64_t o0 = v.off[v.pb];
     const int64_t total = 2 * (v.off[v.pe] - o0) + 16 * (int64_t)(v.pe - v.pb);
     const int64_t stride = (int64_t)gridDim.x * kBlock;
@@ -131,12 +134,14 @@ __global__ __launch_bounds__(kBlock) void tbl_insert(const K *__restrict__ keys,
                                                      const int64_t *__restrict__ pay, TView v,
                                                      int32_t *status)
 {
+    if (skipped(v.skip))
+        return;
     const int64_t o0 = v.off[v.pb], o1 = v.off[v.pe];
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t r = o0 + (int64_t)blockIdx.x * kBlock + threadIdx.x; r < o1; r += stride) {
         const uint64_t h = fmix64(key_bits(keys[r]));
         const int p = upper_index(v.off, v.pb, v.pe, r);
-        if ((int)dest_of(h, v.d) != p) {
+        if ((int)part_of(h, v.d) != p) {
             or_status(status, MDX_DEV_BAD_PARTITIONING);
             continue;
         }
@@ -174,6 +179,8 @@ __global__ __launch_bounds__(kBlock) void tbl_insert(const K *__restrict__ keys,
 // Repeated-key partitions: value := 0 on every slot.
 __global__ __launch_bounds__(kBlock) void grp_reset(TView v)
 {
+    if (skipped(v.skip))
+        return;
     if (!block_any_dup(v))
         return;
     const int64_t o0 = v.off[v.pb];
@@ -194,7 +201,7 @@ __device__ __forceinline__ int64_t dup_row_slot(const K *keys, const TView &v, i
         return -1;
     const uint64_t h = fmix64(key_bits(keys[r]));
     const int p = upper_index(v.off, v.pb, v.pe, r);
-    if (!v.flags[p] || (int)dest_of(h, v.d) != p)
+    if (!v.flags[p] || (int)part_of(h, v.d) != p)
         return -1;
     int64_t sb, H;
     part_slots(v, o0, p, sb, H);
@@ -205,6 +212,8 @@ __device__ __forceinline__ int64_t dup_row_slot(const K *keys, const TView &v, i
 template <typename K>
 __global__ __launch_bounds__(kBlock) void grp_count(const K *__restrict__ keys, TView v)
 {
+    if (skipped(v.skip))
+        return;
     if (!block_any_dup(v))
         return;
     const int64_t o0 = v.off[v.pb], o1 = v.off[v.pe];
@@ -229,6 +238,8 @@ __global__ __launch_bounds__(kBlock) void grp_count(const K *__restrict__ keys, 
 // gstart[s] = value[s] = (partition's first row) + running total.
 __global__ __launch_bounds__(kBlock) void grp_alloc(TView v)
 {
+    if (skipped(v.skip))
+        return;
     if (!block_any_dup(v))
         return;
     const int64_t o0 = v.off[v.pb];
@@ -278,6 +289,8 @@ template <typename K>
 __global__ __launch_bounds__(kBlock) void grp_scatter(const K *__restrict__ keys,
                                                       const int64_t *__restrict__ pay, TView v)
 {
+    if (skipped(v.skip))
+        return;
     if (!block_any_dup(v))
         return;
     const int64_t o0 = v.off[v.pb], o1 = v.off[v.pe];
@@ -306,8 +319,10 @@ __global__ __launch_bounds__(kBlock) void grp_scatter(const K *__restrict__ keys
 // ---- probe -----------------------------------------------------------------
 
 __global__ __launch_bounds__(kBlock) void probe_plan(const int64_t *__restrict__ offR, int64_t n,
-                                                     int P, ProbeWs w)
+                                                     int P, ProbeWs w, const int32_t *skip)
 {
+    if (skipped(skip))
+        return;
     __shared__ int64_t scratch[kWavesPerBlock];
     if (blockIdx.x == 0) {
         sanitize_offsets(offR, w.off, P, n, scratch);
@@ -334,57 +349,14 @@ __global__ __launch_bounds__(kBlock) void probe_plan(const int64_t *__restrict__
         w.status[i] = 0;
 }
 
-// Chained scan step for tile `tile` with count `agg`, run by one full wave.
-// Returns the number of output rows of all earlier tiles.  Every tile that
-// was handed out publishes, so the wait below ends; as a guard it gives up
-// after kSpinLimit polls and reports MDX_DEV_SCAN_TIMEOUT.
-constexpr int64_t kSpinLimit = 1ll << 24;
-
-__device__ int64_t lookback(uint64_t *st, int64_t tile, int64_t agg, int lane, int32_t *status)
-{
-    if (tile == 0) {
-        if (lane == 0)
-            st_agent(st, kFlagIncl | (uint64_t)agg);
-        return 0;
-    }
-    if (lane == 0)
-        st_agent(st + tile, kFlagAgg | (uint64_t)agg);
-    int64_t excl = 0;
-    int64_t j = tile - 1;
-    int64_t polls = 0;
-    for (;;) {
-        const int64_t idx = j - lane;
-        const uint64_t s = idx >= 0 ? ld_agent(st + idx) : kFlagIncl;
-        const uint64_t f = s >> 62;
-        const uint64_t incl = ballot(f == 2);
-        const uint64_t zero = ballot(f == 0);
-        const int L = incl ? __ffsll((unsigned long long)incl) - 1 : kWave - 1;
-        const uint64_t upto = (L == kWave - 1) ? ~0ull : ((2ull << L) - 1);
-        if (zero & upto) {
-            if (++polls > kSpinLimit) {
-                if (lane == 0)
-                    or_status(status, MDX_DEV_SCAN_TIMEOUT);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-        }
-        excl += wave_sum(lane <= L ? (int64_t)(s & kValMask) : 0);
-        if (incl)
-            break;
-        j -= kWave;
-    }
-    if (lane == 0)
-        st_agent(st + tile, kFlagIncl | (uint64_t)(excl + agg));
-    return excl;
-}
-
 template <typename K>
 __global__ __launch_bounds__(kBlock) void probe_chain(const K *__restrict__ pk,
                                                       const int64_t *__restrict__ pv, TView v,
                                                       int group, ProbeWs w, ProbeOut o,
                                                       int32_t *status)
 {
+    if (skipped(v.skip))
+        return;
     constexpr int RP = kProbeRows;
     __shared__ int64_t s_tile, s_excl;
     __shared__ int64_t cw[RP][kWavesPerBlock];
@@ -425,7 +397,7 @@ __global__ __launch_bounds__(kBlock) void probe_chain(const K *__restrict__ pk,
             lv[c] = 0;
             if (r < rend) {
                 const uint64_t h = fmix64(key_bits(kk[c]));
-                if ((int)dest_of(h, v.d) != p) {
+                if ((int)part_of(h, v.d) != p) {
                     bad = true;
                 } else {
                     const int64_t s = find_slot(v.slots, sb, H, h);
@@ -519,6 +491,8 @@ __global__ __launch_bounds__(kBlock) void probe_expand(const K *__restrict__ pk,
                                                        const int64_t *__restrict__ pv, TView v,
                                                        int group, ProbeWs w, ProbeOut o)
 {
+    if (skipped(v.skip))
+        return;
     constexpr int64_t CH = 4096;  // output rows per chunk
     __shared__ int64_t pre[kProbeTile];
     const uint32_t nd = *w.ndefer;
@@ -560,8 +534,11 @@ __global__ __launch_bounds__(kBlock) void probe_expand(const K *__restrict__ pk,
     }
 }
 
-__global__ __launch_bounds__(kBlock) void probe_finalize(int P, ProbeWs w, ProbeOut o)
+__global__ __launch_bounds__(kBlock) void probe_finalize(int P, ProbeWs w, ProbeOut o,
+                                                         const int32_t *skip)
 {
+    if (skipped(skip))
+        return;
     const int64_t TT = w.tile_start[P];
     const int64_t total = TT > 0 ? (int64_t)(ld_agent(w.status + TT - 1) & kValMask) : 0;
     for (int p = threadIdx.x; p <= P; p += kBlock) {
@@ -622,10 +599,10 @@ hipError_t launch_build(const void *keys, const int64_t *pay, int key_bytes, con
 }
 
 hipError_t launch_probe_plan(const int64_t *offR, int64_t n, int32_t P, const ProbeWs &w,
-                             hipStream_t s)
+                             const int32_t *skip, hipStream_t s)
 {
     const int G = device_fill_blocks() / 4 > 0 ? device_fill_blocks() / 4 : 1;
-    hipLaunchKernelGGL(probe_plan, dim3(G), dim3(kBlock), 0, s, offR, n, P, w);
+    hipLaunchKernelGGL(probe_plan, dim3(G), dim3(kBlock), 0, s, offR, n, P, w, skip);
     return hipGetLastError();
 }
 
@@ -639,9 +616,10 @@ hipError_t launch_probe_group(const void *pkeys, const int64_t *ppay, int key_by
     return run_probe_group<int32_t>((const int32_t *)pkeys, ppay, v, group, w, o, status, s);
 }
 
-hipError_t launch_probe_finalize(int32_t P, const ProbeWs &w, const ProbeOut &o, hipStream_t s)
+hipError_t launch_probe_finalize(int32_t P, const ProbeWs &w, const ProbeOut &o,
+                                 const int32_t *skip, hipStream_t s)
 {
-    hipLaunchKernelGGL(probe_finalize, dim3(1), dim3(kBlock), 0, s, P, w, o);
+    hipLaunchKernelGGL(probe_finalize, dim3(1), dim3(kBlock), 0, s, P, w, o, skip);
     return hipGetLastError();
 }
 

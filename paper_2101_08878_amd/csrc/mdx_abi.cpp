@@ -161,7 +161,8 @@ int32_t mdx_trace_kernel(const char *kernel, hipEvent_t *h_starts, hipEvent_t *h
         return MDX_OK;
     }
     static const char *known[] = {"part_hist", "part_scatter", "tbl_init",
-                                  "tbl_insert", "probe_chain", "probe_expand"};
+                                  "tbl_insert", "probe_chain", "probe_expand",
+                                  "seg_scatter", "rj_join"};
     bool ok = false;
     for (const char *k : known)
         ok |= std::string(k) == kernel;
@@ -221,7 +222,7 @@ int32_t mdx_hash_partition(const void *d_keys, const int64_t *d_payload, int64_t
     if (ws_bytes < L.bytes)
         return fail(MDX_ERR_WORKSPACE, "mdx_hash_partition: workspace needs " +
                                            std::to_string(L.bytes) + " bytes");
-    hipError_t e = launch_partition(d_keys, d_payload, n, key_type, P, d_keys_out, d_payload_out,
+    hipError_t e = launch_partition(d_keys, d_payload, n, key_type, P, 0, d_keys_out, d_payload_out,
                                     d_offsets, d_ws, stream);
     return e == hipSuccess ? MDX_OK : hip_fail(e, W);
 }
@@ -251,6 +252,7 @@ static TView make_view(const mdx_table &t, const int64_t *off, int32_t pb, int32
     v.pb = pb;
     v.pe = pe;
     v.d = make_dest(t.P);
+    v.skip = nullptr;
     return v;
 }
 
@@ -383,12 +385,12 @@ int32_t mdx_join_probe(const mdx_table *h_table, const void *d_keys, const int64
     o.rpay = d_out_rpay;
     o.cap = out_capacity;
     o.offsets = d_out_offsets;
-    hipError_t e = launch_probe_plan(d_offsets, n, P, w, stream);
+    hipError_t e = launch_probe_plan(d_offsets, n, P, w, nullptr, stream);
     if (e == hipSuccess)
         e = launch_probe_group(d_keys, d_payload, kt, P, make_view(t, t.d_offsets, 0, P), 0, w, o,
                                d_status, stream);
     if (e == hipSuccess)
-        e = launch_probe_finalize(P, w, o, stream);
+        e = launch_probe_finalize(P, w, o, nullptr, stream);
     return e == hipSuccess ? MDX_OK : hip_fail(e, W);
 }
 
@@ -396,58 +398,98 @@ int32_t mdx_join_probe(const mdx_table *h_table, const void *d_keys, const int64
 
 namespace {
 
+// How mdx_merge splits partitions into sub-buckets for the radix join: each
+// partition into Q = 2^qbits sub-buckets by the top hash bits, sized so that
+// an average sub-bucket's build rows fill ~80% of an LDS table.  The first
+// pass partitions by (p, top q1bits) with a fan-out of at most 128 (long,
+// coalesced output runs); the segmented second pass splits each of those
+// buckets by the next q2bits (at most 256 ways).
+struct MergePlan {
+    int qbits, q1bits, q2bits;
+};
+
+MergePlan merge_plan(int64_t nL, int32_t P)
+{
+    MergePlan m;
+    const double per = 0.8 * kJoinCap;
+    const double want = (double)nL / ((double)P * per);
+    m.qbits = want <= 1.0 ? 0 : ceil_log2((int64_t)(want + 0.999999));
+    // keep the sub-bucket count bounded; oversized sub-buckets fall back to
+    // the global-table join
+    while (m.qbits > 0 && ((int64_t)P << m.qbits) > (int64_t)1 << 22)
+        --m.qbits;
+    for (;; --m.qbits) {
+        m.q1bits = 0;
+        while (m.q1bits < m.qbits && (P << (m.q1bits + 1)) <= 128)
+            ++m.q1bits;
+        m.q2bits = m.qbits - m.q1bits;
+        while (m.q2bits > 8) {  // the segmented pass splits at most 256 ways
+            ++m.q1bits;
+            --m.q2bits;
+        }
+        // the first pass handles at most MDX_MAX_P destinations
+        if (m.qbits == 0 || ((int64_t)P << m.q1bits) <= MDX_MAX_P)
+            break;
+    }
+    return m;
+}
+
 struct MergeLayout {
+    MergePlan plan;
+    int64_t nA, S;  // first-pass destinations, sub-buckets
     PartLayout pl, pr;
+    SegLayout sl, sr;
+    RJoinLayout jl;
     TableLayout tl;
     ProbeLayout ql;
-    size_t partL_off, partR_off, lk_off, lv_off, offL_off, rk_off, rv_off, offR_off, table_off,
-        probe_off, bytes;
+    size_t partL_off, partR_off, lk1_off, lv1_off, rk1_off, rv1_off, offAL_off, offAR_off,
+        offPL_off, offPR_off, segL_off, segR_off, lk2_off, lv2_off, rk2_off, rv2_off, subL_off,
+        subR_off, rjoin_off, table_off, probe_off, bytes;
 };
 
 MergeLayout merge_layout(int64_t nL, int64_t nR, int32_t P, int32_t kt)
 {
     MergeLayout M;
-    M.pl = part_layout(nL, P);
-    M.pr = part_layout(nR, P);
+    M.plan = merge_plan(nL, P);
+    M.nA = (int64_t)P << M.plan.q1bits;
+    M.S = (int64_t)P << M.plan.qbits;
+    M.pl = part_layout(nL, (int32_t)M.nA);
+    M.pr = part_layout(nR, (int32_t)M.nA);
+    M.sl = seg_layout(nL, M.nA, M.plan.q2bits);
+    M.sr = seg_layout(nR, M.nA, M.plan.q2bits);
+    M.jl = rjoin_layout(nR, P, M.plan.qbits);
     M.tl = table_layout(nL, P);
     M.ql = probe_layout(nR, P);
+    const size_t kL = (size_t)(nL > 0 ? nL : 1), kR = (size_t)(nR > 0 ? nR : 1);
+    const bool two = M.plan.q2bits > 0;
     size_t o = 0;
-    M.partL_off = o;
-    o += align_up(M.pl.bytes);
-    M.partR_off = o;
-    o += align_up(M.pr.bytes);
-    M.lk_off = o;
-    o += align_up((size_t)(nL > 0 ? nL : 1) * kt);
-    M.lv_off = o;
-    o += align_up((size_t)(nL > 0 ? nL : 1) * 8);
-    M.offL_off = o;
-    o += align_up((size_t)(P + 1) * 8);
-    M.rk_off = o;
-    o += align_up((size_t)(nR > 0 ? nR : 1) * kt);
-    M.rv_off = o;
-    o += align_up((size_t)(nR > 0 ? nR : 1) * 8);
-    M.offR_off = o;
-    o += align_up((size_t)(P + 1) * 8);
-    M.table_off = o;
-    o += align_up(M.tl.bytes);
-    M.probe_off = o;
-    o += align_up(M.ql.bytes);
+    auto take = [&](size_t &field, size_t bytes) {
+        field = o;
+        o += align_up(bytes);
+    };
+    take(M.partL_off, M.pl.bytes);
+    take(M.partR_off, M.pr.bytes);
+    take(M.lk1_off, kL * kt);
+    take(M.lv1_off, kL * 8);
+    take(M.rk1_off, kR * kt);
+    take(M.rv1_off, kR * 8);
+    take(M.offAL_off, (size_t)(M.nA + 1) * 8);
+    take(M.offAR_off, (size_t)(M.nA + 1) * 8);
+    take(M.offPL_off, (size_t)(P + 1) * 8);
+    take(M.offPR_off, (size_t)(P + 1) * 8);
+    take(M.segL_off, two ? M.sl.bytes : 0);
+    take(M.segR_off, two ? M.sr.bytes : 0);
+    take(M.lk2_off, two ? kL * kt : 0);
+    take(M.lv2_off, two ? kL * 8 : 0);
+    take(M.rk2_off, two ? kR * kt : 0);
+    take(M.rv2_off, two ? kR * 8 : 0);
+    take(M.subL_off, two ? (size_t)(M.S + 1) * 8 : 0);
+    take(M.subR_off, two ? (size_t)(M.S + 1) * 8 : 0);
+    take(M.rjoin_off, M.jl.bytes);
+    take(M.table_off, M.tl.bytes);
+    take(M.probe_off, M.ql.bytes);
     M.bytes = o;
     return M;
-}
-
-// Partitions per group: a group's tables (2 slots of 16 bytes per build
-// row) should stay resident in the last-level cache while it is probed.
-int32_t auto_group(int64_t nL, int32_t P)
-{
-    const double per_part = (2.0 * (double)nL / P + 16.0) * 16.0;
-    const double target = 128.0 * 1024 * 1024;
-    int32_t g = (int32_t)(target / per_part);
-    if (g < 1)
-        g = 1;
-    if (g > P)
-        g = P;
-    return g;
 }
 
 }  // namespace
@@ -470,8 +512,7 @@ int32_t mdx_merge(const void *d_left_keys, const int64_t *d_left_payload, int64_
                   const void *d_right_keys, const int64_t *d_right_payload, int64_t n_right,
                   int32_t key_type, int32_t P, void *d_ws, size_t ws_bytes, void *d_out_key,
                   int64_t *d_out_lpay, int64_t *d_out_rpay, int64_t out_capacity,
-                  int64_t *d_out_offsets, int32_t *d_status, int32_t group_partitions,
-                  hipStream_t stream)
+                  int64_t *d_out_offsets, int32_t *d_status, hipStream_t stream)
 {
     g_err.clear();
     const char *W = "mdx_merge";
@@ -486,8 +527,6 @@ int32_t mdx_merge(const void *d_left_keys, const int64_t *d_left_payload, int64_
     if (int32_t e = check_outputs(d_out_key, d_out_lpay, d_out_rpay, out_capacity, key_type,
                                   d_out_offsets, d_status, W))
         return e;
-    if (group_partitions < 0)
-        return fail(MDX_ERR_INVALID, "mdx_merge: group_partitions < 0");
     const MergeLayout M = merge_layout(n_left, n_right, P, key_type);
     if (!d_ws || !aligned(d_ws, kAlign))
         return fail(MDX_ERR_INVALID, "mdx_merge: workspace null or not 256-byte aligned");
@@ -500,42 +539,77 @@ int32_t mdx_merge(const void *d_left_keys, const int64_t *d_left_payload, int64_
         return fail(MDX_ERR_INVALID, "mdx_merge: workspace overlaps the output");
 
     char *b = (char *)d_ws;
-    void *lk = b + M.lk_off, *rk = b + M.rk_off;
-    int64_t *lv = (int64_t *)(b + M.lv_off), *rv = (int64_t *)(b + M.rv_off);
-    int64_t *offL = (int64_t *)(b + M.offL_off), *offR = (int64_t *)(b + M.offR_off);
-
-    hipError_t e = launch_partition(d_left_keys, d_left_payload, n_left, key_type, P, lk, lv, offL,
-                                    b + M.partL_off, stream);
-    if (e == hipSuccess)
-        e = launch_partition(d_right_keys, d_right_payload, n_right, key_type, P, rk, rv, offR,
-                             b + M.partR_off, stream);
-    if (e != hipSuccess)
-        return hip_fail(e, W);
-
-    mdx_table t = carve_table(b + M.table_off, M.tl.bytes, n_left, P, key_type);
-    const ProbeWs w = probe_ws(b + M.probe_off, M.ql);
+    const MergePlan &pl = M.plan;
+    const int nA = (int)M.nA;
+    void *lk1 = b + M.lk1_off, *rk1 = b + M.rk1_off;
+    int64_t *lv1 = (int64_t *)(b + M.lv1_off), *rv1 = (int64_t *)(b + M.rv1_off);
+    int64_t *offAL = (int64_t *)(b + M.offAL_off), *offAR = (int64_t *)(b + M.offAR_off);
     ProbeOut o;
     o.key = d_out_key;
     o.lpay = d_out_lpay;
     o.rpay = d_out_rpay;
     o.cap = out_capacity;
     o.offsets = d_out_offsets;
-    e = launch_table_setup(nullptr, 0, nullptr, t.d_flags, t.d_bump, P, stream);
+
+    // 1. partition both tables by (partition, top q1bits of the hash)
+    hipError_t e = launch_partition(d_left_keys, d_left_payload, n_left, key_type, P, pl.q1bits,
+                                    lk1, lv1, offAL, b + M.partL_off, stream);
     if (e == hipSuccess)
-        e = launch_probe_plan(offR, n_right, P, w, stream);
-    const int32_t gsz = group_partitions > 0 ? (group_partitions < P ? group_partitions : P)
-                                             : auto_group(n_left, P);
-    int group = 0;
-    for (int32_t pb = 0; pb < P && e == hipSuccess; pb += gsz, ++group) {
-        const int32_t pe = pb + gsz < P ? pb + gsz : P;
-        // Every group reuses the start of the table region.
-        const TView v = make_view(t, offL, pb, pe);
-        e = launch_build(lk, lv, key_type, v, d_status, stream);
+        e = launch_partition(d_right_keys, d_right_payload, n_right, key_type, P, pl.q1bits, rk1,
+                             rv1, offAR, b + M.partR_off, stream);
+
+    // 2. split every first-pass bucket by the next q2bits: sub-buckets
+    const void *lk = lk1, *rk = rk1;
+    const int64_t *lv = lv1, *rv = rv1, *subL = offAL, *subR = offAR;
+    if (pl.q2bits > 0 && e == hipSuccess) {
+        void *lk2 = b + M.lk2_off, *rk2 = b + M.rk2_off;
+        int64_t *lv2 = (int64_t *)(b + M.lv2_off), *rv2 = (int64_t *)(b + M.rv2_off);
+        int64_t *sL = (int64_t *)(b + M.subL_off), *sR = (int64_t *)(b + M.subR_off);
+        e = launch_seg_partition(lk1, lv1, n_left, key_type, offAL, nA, pl.q1bits, pl.q2bits, lk2,
+                                 lv2, sL, b + M.segL_off, nullptr, stream);
         if (e == hipSuccess)
-            e = launch_probe_group(rk, rv, key_type, P, v, group, w, o, d_status, stream);
+            e = launch_seg_partition(rk1, rv1, n_right, key_type, offAR, nA, pl.q1bits, pl.q2bits,
+                                     rk2, rv2, sR, b + M.segR_off, nullptr, stream);
+        lk = lk2;
+        rk = rk2;
+        lv = lv2;
+        rv = rv2;
+        subL = sL;
+        subR = sR;
     }
+
+    // 3. radix join of every sub-bucket in LDS, if every build sub-bucket fits
+    const RJoinWs jw = rjoin_ws(b + M.rjoin_off, M.jl);
     if (e == hipSuccess)
-        e = launch_probe_finalize(P, w, o, stream);
+        e = launch_rjoin_plan(subL, subR, M.S, jw, stream);
+    if (e == hipSuccess)
+        e = launch_rjoin(lk, lv, subL, rk, rv, subR, key_type, P, pl.qbits, jw, o, d_status,
+                         stream);
+    if (e == hipSuccess)
+        e = launch_rjoin_finalize(P, pl.qbits, jw, o, stream);
+
+    // 4. otherwise (a sub-bucket too large for LDS: heavy key repetition),
+    // the global-table join over the first-pass output; its kernels do
+    // nothing when the radix join ran.
+    int64_t *offPL = (int64_t *)(b + M.offPL_off), *offPR = (int64_t *)(b + M.offPR_off);
+    mdx_table t = carve_table(b + M.table_off, M.tl.bytes, n_left, P, key_type);
+    const ProbeWs w = probe_ws(b + M.probe_off, M.ql);
+    if (e == hipSuccess)
+        e = launch_gather_offsets(offAL, P, 1 << pl.q1bits, offPL, stream);
+    if (e == hipSuccess)
+        e = launch_gather_offsets(offAR, P, 1 << pl.q1bits, offPR, stream);
+    if (e == hipSuccess)
+        e = launch_table_setup(offPL, n_left, t.d_offsets, t.d_flags, t.d_bump, P, stream);
+    TView v = make_view(t, t.d_offsets, 0, P);
+    v.skip = jw.use;
+    if (e == hipSuccess)
+        e = launch_build(lk1, lv1, key_type, v, d_status, stream);
+    if (e == hipSuccess)
+        e = launch_probe_plan(offPR, n_right, P, w, jw.use, stream);
+    if (e == hipSuccess)
+        e = launch_probe_group(rk1, rv1, key_type, P, v, 0, w, o, d_status, stream);
+    if (e == hipSuccess)
+        e = launch_probe_finalize(P, w, o, jw.use, stream);
     return e == hipSuccess ? MDX_OK : hip_fail(e, W);
 }
 

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "mdx.h"
+
 namespace mdx {
 
 constexpr int kWave = 64;
@@ -31,17 +33,35 @@ __device__ __forceinline__ uint64_t key_bits(K k)
     return (uint64_t)(int64_t)k;
 }
 
-// Destination p = h mod P (unsigned).  Power-of-two P uses a mask.
+// Destination of a hash: the partition p = h mod P (unsigned; power-of-two P
+// uses a mask), optionally refined by the top `sbits` bits of h into
+// sub-bucket q: d = p * 2^sbits + q.  With sbits = 0 the destination is the
+// partition itself.
 struct Dest {
     uint64_t P;
     uint64_t mask;  // P - 1 when P is a power of two
     int32_t pow2;
-    int32_t nbits;  // bits needed to write P - 1 (0 for P = 1)
+    int32_t sbits;  // sub-bucket bits taken from the top of h
+    int32_t ndest;  // P << sbits
+    int32_t nbits;  // bits needed to write ndest - 1 (0 for ndest = 1)
 };
+
+__device__ __forceinline__ uint32_t part_of(uint64_t h, const Dest &d)
+{
+    return d.pow2 ? (uint32_t)(h & d.mask) : (uint32_t)(h % d.P);
+}
 
 __device__ __forceinline__ uint32_t dest_of(uint64_t h, const Dest &d)
 {
-    return d.pow2 ? (uint32_t)(h & d.mask) : (uint32_t)(h % d.P);
+    const uint32_t p = part_of(h, d);
+    return d.sbits ? ((p << d.sbits) | (uint32_t)(h >> (64 - d.sbits))) : p;
+}
+
+// Bits [64 - shift - bits, 64 - shift) of h: the sub-bucket digit below the
+// `shift` top bits already used.
+__device__ __forceinline__ uint32_t digit_of(uint64_t h, int shift, int bits)
+{
+    return bits ? (uint32_t)((h << shift) >> (64 - bits)) : 0u;
 }
 
 // ---- wave primitives ------------------------------------------------------
@@ -174,5 +194,58 @@ __device__ __forceinline__ int upper_index(const int64_t *a, int lo, int hi, int
     }
     return l;
 }
+
+// ---- chained scan over ordered tiles (decoupled look-back) -------------------
+// Status word of a tile: flag in the top 2 bits (1: its own count is
+// published, 2: its inclusive prefix is published), value below.
+constexpr uint64_t kFlagAgg = 1ull << 62;
+constexpr uint64_t kFlagIncl = 2ull << 62;
+constexpr uint64_t kValMask = (1ull << 62) - 1;
+constexpr int64_t kSpinLimit = 1ll << 24;
+
+// Chained scan step for tile `tile` with count `agg`, run by one full wave.
+// Returns the number of output rows of all earlier tiles.  Every tile that
+// was handed out publishes, so the wait below ends; as a guard it gives up
+// after kSpinLimit polls and reports MDX_DEV_SCAN_TIMEOUT.
+
+__device__ inline int64_t lookback(uint64_t *st, int64_t tile, int64_t agg, int lane, int32_t *status)
+{
+    if (tile == 0) {
+        if (lane == 0)
+            st_agent(st, kFlagIncl | (uint64_t)agg);
+        return 0;
+    }
+    if (lane == 0)
+        st_agent(st + tile, kFlagAgg | (uint64_t)agg);
+    int64_t excl = 0;
+    int64_t j = tile - 1;
+    int64_t polls = 0;
+    for (;;) {
+        const int64_t idx = j - lane;
+        const uint64_t s = idx >= 0 ? ld_agent(st + idx) : kFlagIncl;
+        const uint64_t f = s >> 62;
+        const uint64_t incl = ballot(f == 2);
+        const uint64_t zero = ballot(f == 0);
+        const int L = incl ? __ffsll((unsigned long long)incl) - 1 : kWave - 1;
+        const uint64_t upto = (L == kWave - 1) ? ~0ull : ((2ull << L) - 1);
+        if (zero & upto) {
+            if (++polls > kSpinLimit) {
+                if (lane == 0)
+                    or_status(status, MDX_DEV_SCAN_TIMEOUT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        excl += wave_sum(lane <= L ? (int64_t)(s & kValMask) : 0);
+        if (incl)
+            break;
+        j -= kWave;
+    }
+    if (lane == 0)
+        st_agent(st + tile, kFlagIncl | (uint64_t)(excl + agg));
+    return excl;
+}
+
 
 }  // namespace mdx

@@ -17,16 +17,23 @@ inline size_t align_up(size_t x, size_t a = kAlign)
     return (x + a - 1) / a * a;
 }
 
-inline Dest make_dest(int32_t P)
+inline int ceil_log2(int64_t x)
+{
+    int b = 0;
+    while (b < 62 && ((int64_t)1 << b) < x)
+        ++b;
+    return b;
+}
+
+inline Dest make_dest(int32_t P, int sbits = 0)
 {
     Dest d;
     d.P = (uint64_t)P;
     d.pow2 = (P & (P - 1)) == 0;
     d.mask = d.pow2 ? (uint64_t)(P - 1) : 0;
-    int b = 0;
-    while (b < 31 && ((1u << b) < (uint32_t)P))
-        ++b;
-    d.nbits = b;
+    d.sbits = sbits;
+    d.ndest = P << sbits;
+    d.nbits = ceil_log2(d.ndest);
     return d;
 }
 
@@ -63,9 +70,105 @@ inline PartLayout part_layout(int64_t n, int32_t P)
     return L;
 }
 
+// Stable partition into make_dest(P, sbits).ndest destinations; off has
+// ndest + 1 entries; ws holds part_layout(n, ndest).bytes.
 hipError_t launch_partition(const void *keys, const int64_t *pay, int64_t n, int key_bytes,
-                            int32_t P, void *keys_out, int64_t *pay_out, int64_t *off,
+                            int32_t P, int sbits, void *keys_out, int64_t *pay_out, int64_t *off,
                             void *ws, hipStream_t s);
+
+// ---- segmented partition (second split of the join) -------------------------
+// Segment a (rows [segoff[a], segoff[a+1]) of an already partitioned table)
+// is split stably into 2^bits destinations by digit_of(h, shift, bits);
+// destination (a, q) lands at [outoff[a 2^bits + q], outoff[a 2^bits + q + 1]).
+constexpr int kSegRows = 16;                    // rows per thread
+constexpr int kSegTile = kBlock * kSegRows;     // 4096 rows per tile
+constexpr int kSegChunkTiles = 8;               // tiles per scan chunk
+constexpr int kSegMaxDest = 256;
+
+struct SegLayout {
+    int64_t max_tiles, max_chunks;
+    size_t tile_start_off, chunk_start_off, cnt_off, csum_off, bytes;
+};
+
+inline SegLayout seg_layout(int64_t n, int64_t nseg, int bits)
+{
+    SegLayout L;
+    const int64_t D = (int64_t)1 << bits;
+    L.max_tiles = (n + kSegTile - 1) / kSegTile + nseg;
+    L.max_chunks = L.max_tiles / kSegChunkTiles + nseg + 1;
+    size_t o = 0;
+    L.tile_start_off = o;
+    o += align_up((size_t)(nseg + 1) * sizeof(int64_t));
+    L.chunk_start_off = o;
+    o += align_up((size_t)(nseg + 1) * sizeof(int64_t));
+    L.cnt_off = o;
+    o += align_up((size_t)L.max_tiles * D * sizeof(uint32_t));
+    L.csum_off = o;
+    o += align_up((size_t)L.max_chunks * D * sizeof(int64_t));
+    L.bytes = o;
+    return L;
+}
+
+// gate (optional, device): when *gate == 0 the scatter is skipped.
+hipError_t launch_seg_partition(const void *keys, const int64_t *pay, int64_t n, int key_bytes,
+                                const int64_t *segoff, int64_t nseg, int shift, int bits,
+                                void *keys_out, int64_t *pay_out, int64_t *outoff, void *ws,
+                                const int32_t *gate, hipStream_t s);
+
+// ---- radix join (LDS tables per sub-bucket) ---------------------------------
+// Sub-bucket s of S = P 2^qbits holds build rows [subL[s], subL[s+1]) and
+// probe rows [subR[s], subR[s+1]); partition p owns sub-buckets
+// [p 2^qbits, (p+1) 2^qbits).
+constexpr int kJoinThreads = 1024;
+constexpr int kJoinCap = 7680;        // build rows per LDS table
+constexpr int kJoinHeads = 4096;      // chain heads per LDS table
+constexpr int kJoinRows = 4;          // probe rows per thread per chunk
+constexpr int kJoinChunk = kJoinThreads * kJoinRows;
+
+struct RJoinLayout {
+    int64_t S, max_chunks;
+    size_t chunk_start_off, status_off, tile_base_off, misc_off, bytes;
+};
+
+inline RJoinLayout rjoin_layout(int64_t nR, int32_t P, int qbits)
+{
+    RJoinLayout L;
+    L.S = (int64_t)P << qbits;
+    L.max_chunks = (nR + kJoinChunk - 1) / kJoinChunk + L.S;
+    size_t o = 0;
+    L.chunk_start_off = o;
+    o += align_up((size_t)(L.S + 1) * sizeof(int64_t));
+    L.status_off = o;
+    o += align_up((size_t)L.max_chunks * sizeof(uint64_t));
+    L.tile_base_off = o;
+    o += align_up((size_t)L.max_chunks * sizeof(int64_t));
+    L.misc_off = o;  // ticket (u32), use flag (i32)
+    o += align_up(64);
+    L.bytes = o;
+    return L;
+}
+
+struct RJoinWs {
+    int64_t *chunk_start;
+    uint64_t *status;
+    int64_t *tile_base;
+    uint32_t *ticket;
+    int32_t *use;  // 1: every build sub-bucket fits an LDS table
+    int64_t max_chunks;
+};
+
+inline RJoinWs rjoin_ws(void *base, const RJoinLayout &L)
+{
+    char *b = (char *)base;
+    RJoinWs w;
+    w.chunk_start = (int64_t *)(b + L.chunk_start_off);
+    w.status = (uint64_t *)(b + L.status_off);
+    w.tile_base = (int64_t *)(b + L.tile_base_off);
+    w.ticket = (uint32_t *)(b + L.misc_off);
+    w.use = (int32_t *)(b + L.misc_off + 16);
+    w.max_chunks = L.max_chunks;
+    return w;
+}
 
 // ---- join table -------------------------------------------------------------
 // Partition p of a view over partitions [pb, pe) owns slots
@@ -109,6 +212,7 @@ struct TView {
     int64_t *bump;       // [P]
     int32_t pb, pe;
     Dest d;
+    const int32_t *skip;  // optional: kernels do nothing while *skip != 0
 };
 
 // ---- probe ------------------------------------------------------------------
@@ -212,11 +316,26 @@ hipError_t launch_table_setup(const int64_t *off_in, int64_t n, int64_t *off_tab
 // Probe: plan tiles from the probe offsets (sanitized for n probe rows, once
 // per probe), probe one view (group g), finalize the output offsets.
 hipError_t launch_probe_plan(const int64_t *offR, int64_t n, int32_t P, const ProbeWs &w,
-                             hipStream_t s);
+                             const int32_t *skip, hipStream_t s);
 hipError_t launch_probe_group(const void *pkeys, const int64_t *ppay, int key_bytes, int32_t P,
                               const TView &v, int group, const ProbeWs &w, const ProbeOut &o,
                               int32_t *status, hipStream_t s);
 hipError_t launch_probe_finalize(int32_t P, const ProbeWs &w, const ProbeOut &o,
+                                 const int32_t *skip, hipStream_t s);
+
+// Radix join: plan (chunk plan over the probe sub-buckets, the LDS-fit flag
+// from the build sub-buckets, cleared chained scan), join, output offsets.
+hipError_t launch_rjoin_plan(const int64_t *subL, const int64_t *subR, int64_t S,
+                             const RJoinWs &w, hipStream_t s);
+hipError_t launch_rjoin(const void *lk, const int64_t *lv, const int64_t *subL, const void *rk,
+                        const int64_t *rv, const int64_t *subR, int key_bytes, int32_t P,
+                        int qbits, const RJoinWs &w, const ProbeOut &o, int32_t *status,
+                        hipStream_t s);
+hipError_t launch_rjoin_finalize(int32_t P, int qbits, const RJoinWs &w, const ProbeOut &o,
+                                 hipStream_t s);
+
+// Copy every `stride`-th entry of a[0..P*stride] into out[0..P].
+hipError_t launch_gather_offsets(const int64_t *a, int32_t P, int stride, int64_t *out,
                                  hipStream_t s);
 
 }  // namespace mdx

@@ -27,7 +27,7 @@ __global__ __launch_bounds__(kBlock) void part_hist(const K *__restrict__ keys, 
 {
     extern __shared__ uint32_t hist[];
     const int tid = threadIdx.x;
-    const int P = (int)d.P;
+    const int P = d.ndest;  // destinations
     for (int p = tid; p < P; p += kBlock)
         hist[p] = 0;
     const int64_t tile = blockIdx.x;
@@ -147,16 +147,19 @@ __device__ inline void lds_excl_scan_u32(uint32_t *a, int P, int64_t *scratch)
     __syncthreads();
 }
 
-template <typename K, int R>
-__global__ __launch_bounds__(kBlock) void part_scatter(
-    const K *__restrict__ keys, const int64_t *__restrict__ pay, int64_t n, Dest d,
-    const int64_t *__restrict__ off, const int64_t *__restrict__ pre, int64_t ntiles,
-    K *__restrict__ keys_out, int64_t *__restrict__ pay_out)
+// Stable scatter of one tile, rows [row0, row_end) (at most 256 R of them).
+// dfn(h) gives a row's destination in [0, D); base_of(d) the output position
+// of the tile's first row with destination d.  Wave w owns the contiguous
+// rows [row0 + 64 R w, row0 + 64 R (w+1)); step c reads 64 consecutive rows.
+template <typename K, int R, typename DestFn, typename BaseFn>
+__device__ __forceinline__ void scatter_tile(const K *__restrict__ keys,
+                                             const int64_t *__restrict__ pay, int64_t row0,
+                                             int64_t row_end, int D, int nbits, DestFn dfn,
+                                             BaseFn base_of, K *__restrict__ keys_out,
+                                             int64_t *__restrict__ pay_out, unsigned char *smem)
 {
     constexpr int T = kBlock * R;
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int P = (int)d.P;
-    const ScatterLds L = scatter_lds(T, P, (int)sizeof(K));
+    const ScatterLds L = scatter_lds(T, D, (int)sizeof(K));
     int64_t *stage_v = (int64_t *)(smem + L.stage_v);
     K *stage_k = (K *)(smem + L.stage_k);
     uint16_t *stage_p = (uint16_t *)(smem + L.stage_p);
@@ -166,38 +169,33 @@ __global__ __launch_bounds__(kBlock) void part_scatter(
     int64_t *scratch = (int64_t *)(smem + L.scratch);
 
     const int tid = threadIdx.x, w = tid / kWave, lane = tid & (kWave - 1);
-    const int64_t tile = blockIdx.x;
-    const int64_t row0 = tile * (int64_t)T;
-
-    for (int i = tid; i < kWavesPerBlock * P; i += kBlock)
+    for (int i = tid; i < kWavesPerBlock * D; i += kBlock)
         whist[i] = 0;
-    for (int p = tid; p < P; p += kBlock)
-        gbase[p] = off[p] + pre[(int64_t)p * ntiles + tile];
+    for (int p = tid; p < D; p += kBlock)
+        gbase[p] = base_of(p);
 
-    // Wave w owns the contiguous rows [wrow0, wrow0 + 64 R) of the tile;
-    // step c reads 64 consecutive rows.
     const int64_t wrow0 = row0 + (int64_t)w * kWave * R;
     K kr[R];
     int64_t vr[R];
 #pragma unroll
     for (int c = 0; c < R; ++c) {
         const int64_t r = wrow0 + (int64_t)c * kWave + lane;
-        const bool valid = r < n;
+        const bool valid = r < row_end;
         kr[c] = valid ? __builtin_nontemporal_load(keys + r) : K(0);
         vr[c] = valid ? __builtin_nontemporal_load(pay + r) : 0;
     }
     __syncthreads();
 
     // Rank every row among the earlier rows of its wave with its destination.
-    uint32_t *wh = whist + w * P;
+    uint32_t *wh = whist + w * D;
     uint32_t pr[R], rk[R];
 #pragma unroll
     for (int c = 0; c < R; ++c) {
         const int64_t r = wrow0 + (int64_t)c * kWave + lane;
-        const bool valid = r < n;
-        const uint32_t p = valid ? dest_of(fmix64(key_bits(kr[c])), d) : 0u;
+        const bool valid = r < row_end;
+        const uint32_t p = valid ? dfn(fmix64(key_bits(kr[c]))) : 0u;
         uint64_t m = ballot(valid);
-        for (int b = 0; b < d.nbits; ++b) {
+        for (int b = 0; b < nbits; ++b) {
             const bool bit = (p >> b) & 1u;
             const uint64_t bb = ballot(bit);
             m &= bit ? bb : ~bb;
@@ -214,23 +212,23 @@ __global__ __launch_bounds__(kBlock) void part_scatter(
     __syncthreads();
 
     // Per destination: tile count, and every wave's offset inside it.
-    for (int p = tid; p < P; p += kBlock) {
+    for (int p = tid; p < D; p += kBlock) {
         uint32_t acc = 0;
 #pragma unroll
         for (int ww = 0; ww < kWavesPerBlock; ++ww) {
-            const uint32_t c = whist[ww * P + p];
-            whist[ww * P + p] = acc;
+            const uint32_t c = whist[ww * D + p];
+            whist[ww * D + p] = acc;
             acc += c;
         }
         tstart[p] = acc;
     }
     __syncthreads();
-    lds_excl_scan_u32(tstart, P, scratch);  // tstart[p]: first staged row of p
-    for (int p = tid; p < P; p += kBlock) {
+    lds_excl_scan_u32(tstart, D, scratch);  // tstart[p]: first staged row of p
+    for (int p = tid; p < D; p += kBlock) {
         const uint32_t t0 = tstart[p];
 #pragma unroll
         for (int ww = 0; ww < kWavesPerBlock; ++ww)
-            whist[ww * P + p] += t0;
+            whist[ww * D + p] += t0;
     }
     __syncthreads();
 
@@ -245,7 +243,7 @@ __global__ __launch_bounds__(kBlock) void part_scatter(
     }
     __syncthreads();
 
-    const int rows = (int)((n - row0) < (int64_t)T ? (n - row0) : (int64_t)T);
+    const int rows = (int)((row_end - row0) < (int64_t)T ? (row_end - row0) : (int64_t)T);
     for (int s = tid; s < rows; s += kBlock) {
         const uint32_t p = stage_p[s];
         const int64_t dst = gbase[p] + (s - (int)tstart[p]);
@@ -255,24 +253,188 @@ __global__ __launch_bounds__(kBlock) void part_scatter(
 }
 
 template <typename K, int R>
-hipError_t run_partition(const K *keys, const int64_t *pay, int64_t n, int32_t P, K *keys_out,
-                         int64_t *pay_out, int64_t *off, void *ws, hipStream_t s)
+__global__ __launch_bounds__(kBlock) void part_scatter(
+    const K *__restrict__ keys, const int64_t *__restrict__ pay, int64_t n, Dest d,
+    const int64_t *__restrict__ off, const int64_t *__restrict__ pre, int64_t ntiles,
+    K *__restrict__ keys_out, int64_t *__restrict__ pay_out)
 {
-    const PartLayout L = part_layout(n, P);
-    const Dest d = make_dest(P);
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int64_t tile = blockIdx.x;
+    scatter_tile<K, R>(
+        keys, pay, tile * (int64_t)(kBlock * R), n, d.ndest, d.nbits,
+        [&](uint64_t h) { return dest_of(h, d); },
+        [&](int p) { return off[p] + pre[(int64_t)p * ntiles + tile]; }, keys_out, pay_out, smem);
+}
+
+// ---- segmented partition -------------------------------------------------------
+// Tiles of 4096 rows never straddle a segment; chunks of 8 tiles never
+// straddle a segment.  A row's position is
+//   outoff[a D + q] + (rows of (a, q) in earlier chunks of a)
+//                   + (rows of (a, q) in earlier tiles of the chunk)
+//                   + (rank inside the tile),
+// i.e. the stable counting-sort position inside segment a.
+
+__global__ __launch_bounds__(kBlock) void seg_plan(const int64_t *__restrict__ segoff, int nseg,
+                                                   int64_t *__restrict__ tile_start,
+                                                   int64_t *__restrict__ chunk_start)
+{
+    __shared__ int64_t scratch[kWavesPerBlock];
+    int64_t tcarry = 0, ccarry = 0;
+    for (int base = 0; base < nseg; base += kBlock) {
+        const int a = base + threadIdx.x;
+        int64_t nt = 0;
+        if (a < nseg)
+            nt = (segoff[a + 1] - segoff[a] + kSegTile - 1) / kSegTile;
+        const int64_t nc = (nt + kSegChunkTiles - 1) / kSegChunkTiles;
+        int64_t tt, ct;
+        const int64_t te = block_excl_scan(nt, scratch, &tt);
+        const int64_t ce = block_excl_scan(nc, scratch, &ct);
+        if (a < nseg) {
+            tile_start[a] = tcarry + te;
+            chunk_start[a] = ccarry + ce;
+        }
+        tcarry += tt;
+        ccarry += ct;
+    }
+    if (threadIdx.x == 0) {
+        tile_start[nseg] = tcarry;
+        chunk_start[nseg] = ccarry;
+    }
+}
+
+// Block = chunk: per-tile digit counts, stored as the exclusive prefix over
+// the chunk's earlier tiles; chunk totals to csum.
+template <typename K>
+__global__ __launch_bounds__(kBlock) void seg_hist(
+    const K *__restrict__ keys, const int64_t *__restrict__ segoff, int nseg,
+    const int64_t *__restrict__ tile_start, const int64_t *__restrict__ chunk_start, int shift,
+    int bits, uint32_t *__restrict__ cnt, int64_t *__restrict__ csum)
+{
+    __shared__ uint32_t hist[kSegMaxDest], run[kSegMaxDest];
+    const int64_t c = blockIdx.x;
+    if (c >= chunk_start[nseg])
+        return;
+    const int D = 1 << bits, tid = threadIdx.x;
+    const int a = upper_index(chunk_start, 0, nseg, c);
+    const int64_t t0 = tile_start[a] + (c - chunk_start[a]) * kSegChunkTiles;
+    const int64_t t1 = t0 + kSegChunkTiles < tile_start[a + 1] ? t0 + kSegChunkTiles
+                                                                : tile_start[a + 1];
+    for (int q = tid; q < D; q += kBlock)
+        run[q] = 0;
+    for (int64_t t = t0; t < t1; ++t) {
+        for (int q = tid; q < D; q += kBlock)
+            hist[q] = 0;
+        const int64_t r0 = segoff[a] + (t - tile_start[a]) * kSegTile;
+        const int64_t r1 = r0 + kSegTile < segoff[a + 1] ? r0 + kSegTile : segoff[a + 1];
+        K k[kSegRows];
+#pragma unroll
+        for (int j = 0; j < kSegRows; ++j) {
+            const int64_t r = r0 + (int64_t)j * kBlock + tid;
+            k[j] = r < r1 ? __builtin_nontemporal_load(keys + r) : K(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kSegRows; ++j) {
+            const int64_t r = r0 + (int64_t)j * kBlock + tid;
+            if (r < r1)
+                atomicAdd(&hist[digit_of(fmix64(key_bits(k[j])), shift, bits)], 1u);
+        }
+        __syncthreads();
+        for (int q = tid; q < D; q += kBlock) {
+            cnt[t * D + q] = run[q];
+            run[q] += hist[q];
+        }
+        __syncthreads();
+    }
+    for (int q = tid; q < D; q += kBlock)
+        csum[c * D + q] = run[q];
+}
+
+// Block = segment: chunk totals -> exclusive prefix over the segment's chunks
+// (in place); destination bases outoff[a D + q].
+__global__ __launch_bounds__(kBlock) void seg_scan(const int64_t *__restrict__ segoff, int nseg,
+                                                   const int64_t *__restrict__ chunk_start,
+                                                   int bits, int64_t *__restrict__ csum,
+                                                   int64_t *__restrict__ outoff)
+{
+    __shared__ int64_t scratch[kWavesPerBlock];
+    __shared__ int64_t tot[kSegMaxDest];
+    const int a = blockIdx.x, D = 1 << bits, tid = threadIdx.x;
+    const int64_t c0 = chunk_start[a], c1 = chunk_start[a + 1];
+    for (int q = tid; q < D; q += kBlock) {
+        int64_t run = 0;
+        for (int64_t c = c0; c < c1; ++c) {
+            const int64_t v = csum[c * D + q];
+            csum[c * D + q] = run;
+            run += v;
+        }
+        tot[q] = run;
+    }
+    __syncthreads();
+    int64_t carry = segoff[a];
+    for (int base = 0; base < D; base += kBlock) {
+        const int q = base + tid;
+        const int64_t v = q < D ? tot[q] : 0;
+        int64_t all;
+        const int64_t ex = block_excl_scan(v, scratch, &all);
+        if (q < D)
+            outoff[(int64_t)a * D + q] = carry + ex;
+        carry += all;
+    }
+    if (a == nseg - 1 && tid == 0)
+        outoff[(int64_t)nseg * D] = segoff[nseg];
+}
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void seg_scatter(
+    const K *__restrict__ keys, const int64_t *__restrict__ pay,
+    const int64_t *__restrict__ segoff, int nseg, const int64_t *__restrict__ tile_start,
+    const int64_t *__restrict__ chunk_start, int shift, int bits,
+    const uint32_t *__restrict__ cnt, const int64_t *__restrict__ csum,
+    const int64_t *__restrict__ outoff, K *__restrict__ keys_out, int64_t *__restrict__ pay_out,
+    const int32_t *gate)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    if (gate && *gate == 0)
+        return;
+    const int64_t t = blockIdx.x;
+    if (t >= tile_start[nseg])
+        return;
+    const int D = 1 << bits;
+    const int a = upper_index(tile_start, 0, nseg, t);
+    const int64_t lt = t - tile_start[a];
+    const int64_t chunk = chunk_start[a] + lt / kSegChunkTiles;
+    const int64_t r0 = segoff[a] + lt * kSegTile;
+    const int64_t r1 = r0 + kSegTile < segoff[a + 1] ? r0 + kSegTile : segoff[a + 1];
+    scatter_tile<K, kSegRows>(
+        keys, pay, r0, r1, D, bits,
+        [&](uint64_t h) { return digit_of(h, shift, bits); },
+        [&](int q) {
+            return outoff[(int64_t)a * D + q] + csum[chunk * D + q] + (int64_t)cnt[t * D + q];
+        },
+        keys_out, pay_out, smem);
+}
+
+template <typename K, int R>
+hipError_t run_partition(const K *keys, const int64_t *pay, int64_t n, int32_t P, int sbits,
+                         K *keys_out, int64_t *pay_out, int64_t *off, void *ws, hipStream_t s)
+{
+    const Dest d = make_dest(P, sbits);
+    const int D = d.ndest;
+    const PartLayout L = part_layout(n, D);
     int64_t *cnt = (int64_t *)((char *)ws + L.cnt_off);
     int64_t *totals = (int64_t *)((char *)ws + L.totals_off);
     if (L.ntiles > 0) {
         trace_begin("part_hist", s);
         hipLaunchKernelGGL((part_hist<K, R>), dim3((unsigned)L.ntiles), dim3(kBlock),
-                           (size_t)P * sizeof(uint32_t), s, keys, n, d, cnt, L.ntiles);
+                           (size_t)D * sizeof(uint32_t), s, keys, n, d, cnt, L.ntiles);
         trace_end("part_hist", s);
     }
-    hipLaunchKernelGGL(part_scan_tiles, dim3((unsigned)P), dim3(kBlock), 0, s, cnt, L.ntiles,
+    hipLaunchKernelGGL(part_scan_tiles, dim3((unsigned)D), dim3(kBlock), 0, s, cnt, L.ntiles,
                        totals);
-    hipLaunchKernelGGL(part_offsets, dim3(1), dim3(kBlock), 0, s, totals, P, off);
+    hipLaunchKernelGGL(part_offsets, dim3(1), dim3(kBlock), 0, s, totals, D, off);
     if (L.ntiles > 0) {
-        const size_t lds = scatter_lds(kBlock * R, P, (int)sizeof(K)).total;
+        const size_t lds = scatter_lds(kBlock * R, D, (int)sizeof(K)).total;
         hipError_t e = hipFuncSetAttribute((const void *)part_scatter<K, R>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess)
@@ -288,22 +450,70 @@ hipError_t run_partition(const K *keys, const int64_t *pay, int64_t n, int32_t P
 }  // namespace
 
 hipError_t launch_partition(const void *keys, const int64_t *pay, int64_t n, int key_bytes,
-                            int32_t P, void *keys_out, int64_t *pay_out, int64_t *off, void *ws,
-                            hipStream_t s)
+                            int32_t P, int sbits, void *keys_out, int64_t *pay_out, int64_t *off,
+                            void *ws, hipStream_t s)
 {
-    const int R = part_rows_per_thread(P);
+    const int R = part_rows_per_thread(P << sbits);
     if (key_bytes == 8) {
         if (R == kPartRowsSmall)
-            return run_partition<int64_t, kPartRowsSmall>((const int64_t *)keys, pay, n, P,
+            return run_partition<int64_t, kPartRowsSmall>((const int64_t *)keys, pay, n, P, sbits,
                                                           (int64_t *)keys_out, pay_out, off, ws, s);
-        return run_partition<int64_t, kPartRowsLarge>((const int64_t *)keys, pay, n, P,
+        return run_partition<int64_t, kPartRowsLarge>((const int64_t *)keys, pay, n, P, sbits,
                                                       (int64_t *)keys_out, pay_out, off, ws, s);
     }
     if (R == kPartRowsSmall)
-        return run_partition<int32_t, kPartRowsSmall>((const int32_t *)keys, pay, n, P,
+        return run_partition<int32_t, kPartRowsSmall>((const int32_t *)keys, pay, n, P, sbits,
                                                       (int32_t *)keys_out, pay_out, off, ws, s);
-    return run_partition<int32_t, kPartRowsLarge>((const int32_t *)keys, pay, n, P,
+    return run_partition<int32_t, kPartRowsLarge>((const int32_t *)keys, pay, n, P, sbits,
                                                   (int32_t *)keys_out, pay_out, off, ws, s);
+}
+
+hipError_t launch_seg_partition(const void *keys, const int64_t *pay, int64_t n, int key_bytes,
+                                const int64_t *segoff, int64_t nseg, int shift, int bits,
+                                void *keys_out, int64_t *pay_out, int64_t *outoff, void *ws,
+                                const int32_t *gate, hipStream_t s)
+{
+    const SegLayout L = seg_layout(n, nseg, bits);
+    char *b = (char *)ws;
+    int64_t *tile_start = (int64_t *)(b + L.tile_start_off);
+    int64_t *chunk_start = (int64_t *)(b + L.chunk_start_off);
+    uint32_t *cnt = (uint32_t *)(b + L.cnt_off);
+    int64_t *csum = (int64_t *)(b + L.csum_off);
+    const int ns = (int)nseg;
+    hipLaunchKernelGGL(seg_plan, dim3(1), dim3(kBlock), 0, s, segoff, ns, tile_start, chunk_start);
+    const size_t lds = scatter_lds(kSegTile, 1 << bits, key_bytes).total;
+    if (key_bytes == 8) {
+        hipLaunchKernelGGL(seg_hist<int64_t>, dim3((unsigned)L.max_chunks), dim3(kBlock), 0, s,
+                           (const int64_t *)keys, segoff, ns, tile_start, chunk_start, shift, bits,
+                           cnt, csum);
+    } else {
+        hipLaunchKernelGGL(seg_hist<int32_t>, dim3((unsigned)L.max_chunks), dim3(kBlock), 0, s,
+                           (const int32_t *)keys, segoff, ns, tile_start, chunk_start, shift, bits,
+                           cnt, csum);
+    }
+    hipLaunchKernelGGL(seg_scan, dim3((unsigned)ns), dim3(kBlock), 0, s, segoff, ns, chunk_start,
+                       bits, csum, outoff);
+    hipError_t e;
+    trace_begin("seg_scatter", s);
+    if (key_bytes == 8) {
+        e = hipFuncSetAttribute((const void *)seg_scatter<int64_t>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(seg_scatter<int64_t>, dim3((unsigned)L.max_tiles), dim3(kBlock), lds, s,
+                           (const int64_t *)keys, pay, segoff, ns, tile_start, chunk_start, shift,
+                           bits, cnt, csum, outoff, (int64_t *)keys_out, pay_out, gate);
+    } else {
+        e = hipFuncSetAttribute((const void *)seg_scatter<int32_t>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(seg_scatter<int32_t>, dim3((unsigned)L.max_tiles), dim3(kBlock), lds, s,
+                           (const int32_t *)keys, pay, segoff, ns, tile_start, chunk_start, shift,
+                           bits, cnt, csum, outoff, (int32_t *)keys_out, pay_out, gate);
+    }
+    trace_end("seg_scatter", s);
+    return hipGetLastError();
 }
 
 }  // namespace mdx

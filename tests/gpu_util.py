@@ -50,12 +50,12 @@ def run_staged_join(kl, vl, kr, vr, P, cap=None):
                 status=int(status.item()), cap=cap)
 
 
-def run_merge(kl, vl, kr, vr, P, cap=None, group=0):
+def run_merge(kl, vl, kr, vr, P, cap=None):
     import paper_2101_08878_amd as mdx
     status = torch.zeros(1, dtype=torch.int32, device="cuda")
     cap = max(len(kr), 1) if cap is None else cap
     ok, ol, orr, off = mdx.mdx_merge(dev(kl), dev(vl), dev(kr), dev(vr), P, out_capacity=cap,
-                                     status=status, group_partitions=group)
+                                     status=status)
     torch.cuda.synchronize()
     return dict(key=host(ok), lpay=host(ol), rpay=host(orr), off=host(off),
                 status=int(status.item()), cap=cap)

@@ -119,7 +119,7 @@ def test_build_probe_merge_validation():
     # merge: bad P, negative capacity, overlapping outputs, small workspace
     args = [FAKE, FAKE + (1 << 30), 10, FAKE + (2 << 30), FAKE + (3 << 30), 10, 8, 4,
             FAKE + (4 << 30), 1 << 30, FAKE + (5 << 30), FAKE + (6 << 30), FAKE + (7 << 30), 10,
-            FAKE + (8 << 30), None, 0, None]
+            FAKE + (8 << 30), None, None]
     bad = list(args); bad[7] = 0
     assert L._merge(*bad) == mdx.MDX_ERR_INVALID
     bad = list(args); bad[13] = -1
@@ -128,5 +128,5 @@ def test_build_probe_merge_validation():
     assert L._merge(*bad) == mdx.MDX_ERR_INVALID
     bad = list(args); bad[9] = 1024
     assert L._merge(*bad) == mdx.MDX_ERR_WORKSPACE
-    bad = list(args); bad[16] = -1
+    bad = list(args); bad[2] = -3
     assert L._merge(*bad) == mdx.MDX_ERR_INVALID

@@ -1,7 +1,11 @@
-"""Parity of mdx_merge (partition both tables, join every partition in
-cache-sized groups) with the oracle, plus the 1E8 x 1E8 workload in the
-launch configuration the benchmark times, checked through properties that
-hold at any size."""
+"""Parity of mdx_merge with the oracle.
+
+mdx_merge partitions both tables, splits every partition into LDS-sized
+sub-buckets and joins each sub-bucket in LDS; when a build sub-bucket is too
+large for LDS (heavily repeated keys) the device switches to the global-table
+join.  Both routes are compared with the oracle here, plus the 1E8 x 1E8
+workload in the launch configuration the benchmark times, checked through
+properties that hold at any size."""
 
 import numpy as np
 import pytest
@@ -9,7 +13,7 @@ import pytest
 import oracle
 from tests.gpu_util import announce, assert_join_equals_oracle, require_gpu, run_merge
 from tests.helpers import part_np
-from workloads import config_inputs, match_fraction_tables, zipf_tables
+from workloads import config_inputs, edge_tables, match_fraction_tables, uniform_tables, zipf_tables
 
 pytestmark = pytest.mark.gpu
 
@@ -19,40 +23,92 @@ def _gpu():
     require_gpu()
 
 
-@pytest.mark.parametrize("group", [0, 1, 3, 4])
-def test_merge_plain_workload(group):
-    announce(f"merge plain group={group}")
+def test_merge_plain_workload():
+    announce("merge plain")
     kl, vl, kr, vr = config_inputs("plain")
-    got = run_merge(kl, vl, kr, vr, 4, group=group)
+    got = run_merge(kl, vl, kr, vr, 4)
     assert_join_equals_oracle(kl, vl, kr, vr, 4, got)
 
 
-@pytest.mark.parametrize("group", [0, 1, 5, 32])
-def test_merge_paper_shape_reduced(group):
-    """The 1E8 workload's generator at 2E6 rows per side, P = 32."""
-    announce(f"merge paper x0.02 group={group}")
-    kl, vl, kr, vr = config_inputs("paper", scale=0.02)
-    got = run_merge(kl, vl, kr, vr, 32, group=group)
+@pytest.mark.parametrize("scale", [0.02, 0.05])
+def test_merge_paper_shape_reduced(scale):
+    """The 1E8 workload's generator at 2E6 and 5E6 rows per side, P = 32
+    (both split passes active)."""
+    announce(f"merge paper x{scale}")
+    kl, vl, kr, vr = config_inputs("paper", scale=scale)
+    got = run_merge(kl, vl, kr, vr, 32)
     assert_join_equals_oracle(kl, vl, kr, vr, 32, got)
+
+
+@pytest.mark.parametrize("P", [1, 3, 7, 64, 257, 4096])
+def test_merge_partition_counts(P):
+    announce(f"merge P={P}")
+    kl, vl, kr, vr = match_fraction_tables(400_000, 300_001, 0.3, seed=P)
+    got = run_merge(kl, vl, kr, vr, P)
+    assert_join_equals_oracle(kl, vl, kr, vr, P, got)
+
+
+@pytest.mark.parametrize("dtype", [np.int64, np.int32])
+def test_merge_repeated_keys_radix(dtype):
+    """Repeated keys whose sub-buckets still fit LDS: chains hold equal keys."""
+    announce(f"merge repeated keys {np.dtype(dtype).name}")
+    kl, vl, kr, vr = uniform_tables(200_000, 150_000, 60_000, seed=6, key_dtype=dtype)
+    total = oracle.join(kl, vl, kr, vr, materialize=False)["total"]
+    got = run_merge(kl, vl, kr, vr, 8, cap=total)
+    assert_join_equals_oracle(kl, vl, kr, vr, 8, got)
 
 
 def test_merge_int32_keys():
     announce("merge int32")
     kl, vl, kr, vr = match_fraction_tables(300_000, 250_000, 0.3, seed=4, key_dtype=np.int32)
-    got = run_merge(kl, vl, kr, vr, 8, group=2)
+    got = run_merge(kl, vl, kr, vr, 8)
     assert_join_equals_oracle(kl, vl, kr, vr, 8, got)
+
+
+def test_merge_fallback_for_oversized_sub_bucket():
+    """20000 build rows of one key: one sub-bucket exceeds the LDS table, so
+    the device must take the global-table join."""
+    announce("merge fallback (one key x 20000)")
+    rng = np.random.default_rng(1)
+    kl = np.concatenate([np.full(20_000, 5, np.int64), rng.integers(10, 10_000, 30_000)])
+    kr = np.concatenate([np.full(50, 5, np.int64), rng.integers(10, 10_000, 20_000)])
+    kl, kr = kl[rng.permutation(kl.size)], kr[rng.permutation(kr.size)]
+    vl, vr = np.arange(kl.size, dtype=np.int64), np.arange(kr.size, dtype=np.int64)
+    total = oracle.join(kl, vl, kr, vr, materialize=False)["total"]
+    got = run_merge(kl, vl, kr, vr, 4, cap=total)
+    assert_join_equals_oracle(kl, vl, kr, vr, 4, got)
 
 
 def test_merge_skewed_reduced():
     announce("merge zipf reduced")
     kl, vl, kr, vr = zipf_tables(15_000, 15_000, 1.1, 10_000, seed=0)
     total = oracle.join(kl, vl, kr, vr, materialize=False)["total"]
-    got = run_merge(kl, vl, kr, vr, 16, cap=total, group=3)
+    got = run_merge(kl, vl, kr, vr, 16, cap=total)
     assert_join_equals_oracle(kl, vl, kr, vr, 16, got)
 
 
+@pytest.mark.parametrize("name", ["empty_left", "empty_right", "both_empty", "all_equal", "extremes",
+                                  "int32_negative", "int32_extremes"])
+def test_merge_edge_tables(name):
+    announce(f"merge edge {name}")
+    kl, vl, kr, vr, _ = edge_tables(name)
+    total = oracle.join(kl, vl, kr, vr, materialize=False)["total"]
+    for P in [1, 5, 32]:
+        got = run_merge(kl, vl, kr, vr, P, cap=max(total, 1))
+        assert_join_equals_oracle(kl, vl, kr, vr, P, got)
+
+
+def test_merge_capacity_overflow():
+    announce("merge capacity overflow")
+    import paper_2101_08878_amd as mdx
+    kl, vl, kr, vr = match_fraction_tables(100_000, 100_000, 0.5, seed=2)
+    got = run_merge(kl, vl, kr, vr, 8, cap=10_000)
+    assert got["off"][-1] == 50_000
+    assert got["status"] & mdx.MDX_DEV_OUTPUT_OVERFLOW
+
+
 def test_merge_paper_scale_properties():
-    """1E8 x 1E8, P = 32, default grouping (what the benchmark times).
+    """1E8 x 1E8, P = 32 (what the benchmark times).
 
     Left keys are a permutation of [0, 1E8), so a right row matches iff its
     key is below 1E8, and then exactly once: the output must be exactly the
