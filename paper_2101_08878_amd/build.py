@@ -27,15 +27,17 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-x", "hip",
-           *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
+def build(verbose: bool = False, extra_flags=(), out: str = LIB) -> str:
+    """Compile libmdx.so; `extra_flags` (e.g. tuning -D defines) and `out`
+    allow building variants elsewhere."""
+    tmp = out + ".tmp"
+    cmd = [HIPCC, *FLAGS, *extra_flags, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-x",
+           "hip", *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -457,7 +457,7 @@ MergeLayout merge_layout(int64_t nL, int64_t nR, int32_t P, int32_t kt)
     M.pr = part_layout(nR, (int32_t)M.nA);
     M.sl = seg_layout(nL, M.nA, M.plan.q2bits);
     M.sr = seg_layout(nR, M.nA, M.plan.q2bits);
-    M.jl = rjoin_layout(nR, P, M.plan.qbits);
+    M.jl = rjoin_layout(P, M.plan.qbits);
     M.tl = table_layout(nL, P);
     M.ql = probe_layout(nR, P);
     const size_t kL = (size_t)(nL > 0 ? nL : 1), kR = (size_t)(nR > 0 ? nR : 1);

@@ -180,6 +180,25 @@ __device__ __forceinline__ void or_status(int32_t *s, int32_t bits)
         __hip_atomic_fetch_or(s, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Tile handled by workgroup b of n.  Workgroups are dispatched round-robin
+// over the 8 XCDs (b mod 8); with MDX_XCD_SWIZZLE each XCD gets a
+// contiguous run of tiles, so neighbouring tiles' partial output lines meet
+// in the same L2.
+#ifndef MDX_XCD_SWIZZLE
+#define MDX_XCD_SWIZZLE 1
+#endif
+__device__ __forceinline__ int64_t tile_of_block(int64_t b, int64_t n)
+{
+#if MDX_XCD_SWIZZLE
+    constexpr int64_t X = 8;
+    const int64_t x = b % X, k = b / X, q = n / X, r = n % X;
+    return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+#else
+    (void)n;
+    return b;
+#endif
+}
+
 // Largest q in [lo, hi) with a[q] <= x, for a non-decreasing a with
 // a[lo] <= x (a has at least hi entries).
 __device__ __forceinline__ int upper_index(const int64_t *a, int lo, int hi, int64_t x)

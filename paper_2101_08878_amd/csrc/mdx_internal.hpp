@@ -40,7 +40,10 @@ inline Dest make_dest(int32_t P, int sbits = 0)
 // ---- partition ------------------------------------------------------------
 // Rows per tile of the partition kernels: 256 threads x R rows.  Small P
 // keeps one tile's rows staged in LDS; large P needs LDS for its counters.
-constexpr int kPartRowsSmall = 16;   // tile 4096 rows, P <= kPartSmallMaxP
+#ifndef MDX_PART_ROWS
+#define MDX_PART_ROWS 16
+#endif
+constexpr int kPartRowsSmall = MDX_PART_ROWS;  // tile 256 R rows, P <= kPartSmallMaxP
 constexpr int kPartRowsLarge = 4;    // tile 1024 rows
 constexpr int kPartSmallMaxP = 256;
 
@@ -80,7 +83,10 @@ hipError_t launch_partition(const void *keys, const int64_t *pay, int64_t n, int
 // Segment a (rows [segoff[a], segoff[a+1]) of an already partitioned table)
 // is split stably into 2^bits destinations by digit_of(h, shift, bits);
 // destination (a, q) lands at [outoff[a 2^bits + q], outoff[a 2^bits + q + 1]).
-constexpr int kSegRows = 16;                    // rows per thread
+#ifndef MDX_SEG_ROWS
+#define MDX_SEG_ROWS 16
+#endif
+constexpr int kSegRows = MDX_SEG_ROWS;          // rows per thread
 constexpr int kSegTile = kBlock * kSegRows;     // 4096 rows per tile
 constexpr int kSegChunkTiles = 8;               // tiles per scan chunk
 constexpr int kSegMaxDest = 256;
@@ -119,29 +125,27 @@ hipError_t launch_seg_partition(const void *keys, const int64_t *pay, int64_t n,
 // Sub-bucket s of S = P 2^qbits holds build rows [subL[s], subL[s+1]) and
 // probe rows [subR[s], subR[s+1]); partition p owns sub-buckets
 // [p 2^qbits, (p+1) 2^qbits).
-constexpr int kJoinThreads = 1024;
+constexpr int kJoinThreads = 512;
 constexpr int kJoinCap = 7680;        // build rows per LDS table
 constexpr int kJoinHeads = 4096;      // chain heads per LDS table
-constexpr int kJoinRows = 4;          // probe rows per thread per chunk
-constexpr int kJoinChunk = kJoinThreads * kJoinRows;
+constexpr int kJoinRows = 16;         // probe rows per thread per batch
+constexpr int kJoinBatch = kJoinThreads * kJoinRows;
 
+// One chained-scan tile per sub-bucket.
 struct RJoinLayout {
-    int64_t S, max_chunks;
-    size_t chunk_start_off, status_off, tile_base_off, misc_off, bytes;
+    int64_t S;
+    size_t status_off, tile_base_off, misc_off, bytes;
 };
 
-inline RJoinLayout rjoin_layout(int64_t nR, int32_t P, int qbits)
+inline RJoinLayout rjoin_layout(int32_t P, int qbits)
 {
     RJoinLayout L;
     L.S = (int64_t)P << qbits;
-    L.max_chunks = (nR + kJoinChunk - 1) / kJoinChunk + L.S;
     size_t o = 0;
-    L.chunk_start_off = o;
-    o += align_up((size_t)(L.S + 1) * sizeof(int64_t));
     L.status_off = o;
-    o += align_up((size_t)L.max_chunks * sizeof(uint64_t));
+    o += align_up((size_t)L.S * sizeof(uint64_t));
     L.tile_base_off = o;
-    o += align_up((size_t)L.max_chunks * sizeof(int64_t));
+    o += align_up((size_t)L.S * sizeof(int64_t));
     L.misc_off = o;  // ticket (u32), use flag (i32)
     o += align_up(64);
     L.bytes = o;
@@ -149,24 +153,22 @@ inline RJoinLayout rjoin_layout(int64_t nR, int32_t P, int qbits)
 }
 
 struct RJoinWs {
-    int64_t *chunk_start;
     uint64_t *status;
     int64_t *tile_base;
     uint32_t *ticket;
     int32_t *use;  // 1: every build sub-bucket fits an LDS table
-    int64_t max_chunks;
+    int64_t S;
 };
 
 inline RJoinWs rjoin_ws(void *base, const RJoinLayout &L)
 {
     char *b = (char *)base;
     RJoinWs w;
-    w.chunk_start = (int64_t *)(b + L.chunk_start_off);
     w.status = (uint64_t *)(b + L.status_off);
     w.tile_base = (int64_t *)(b + L.tile_base_off);
     w.ticket = (uint32_t *)(b + L.misc_off);
     w.use = (int32_t *)(b + L.misc_off + 16);
-    w.max_chunks = L.max_chunks;
+    w.S = L.S;
     return w;
 }
 

@@ -259,7 +259,7 @@ __global__ __launch_bounds__(kBlock) void part_scatter(
     K *__restrict__ keys_out, int64_t *__restrict__ pay_out)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int64_t tile = blockIdx.x;
+    const int64_t tile = tile_of_block(blockIdx.x, gridDim.x);
     scatter_tile<K, R>(
         keys, pay, tile * (int64_t)(kBlock * R), n, d.ndest, d.nbits,
         [&](uint64_t h) { return dest_of(h, d); },
@@ -397,7 +397,7 @@ __global__ __launch_bounds__(kBlock) void seg_scatter(
     extern __shared__ __align__(16) unsigned char smem[];
     if (gate && *gate == 0)
         return;
-    const int64_t t = blockIdx.x;
+    const int64_t t = tile_of_block(blockIdx.x, gridDim.x);
     if (t >= tile_start[nseg])
         return;
     const int D = 1 << bits;
