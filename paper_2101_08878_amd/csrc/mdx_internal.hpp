@@ -125,10 +125,15 @@ hipError_t launch_seg_partition(const void *keys, const int64_t *pay, int64_t n,
 // Sub-bucket s of S = P 2^qbits holds build rows [subL[s], subL[s+1]) and
 // probe rows [subR[s], subR[s+1]); partition p owns sub-buckets
 // [p 2^qbits, (p+1) 2^qbits).
+// One 512-thread workgroup per CU holds a 152 KB table in LDS (of 160 KB).
+// Two half-size workgroups per CU, or one of 1024 threads, measured no
+// faster: the time per sub-bucket is set by the latency of its dependent
+// steps, not by the number of waves.
+constexpr int kJoinPerCu = 1;
 constexpr int kJoinThreads = 512;
-constexpr int kJoinCap = 7680;        // build rows per LDS table
-constexpr int kJoinHeads = 4096;      // chain heads per LDS table
-constexpr int kJoinRows = 16;         // probe rows per thread per batch
+constexpr int kJoinCap = 7680;    // build rows per LDS table
+constexpr int kJoinHeads = 4096;  // chain heads per LDS table
+constexpr int kJoinRows = 16;     // probe rows per thread per batch
 constexpr int kJoinBatch = kJoinThreads * kJoinRows;
 
 // One chained-scan tile per sub-bucket.

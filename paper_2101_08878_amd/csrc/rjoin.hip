@@ -19,19 +19,33 @@
 // Sub-buckets are numbered partition-major, so partition p's output is the
 // contiguous range [out_off[p], out_off[p+1]).  Global memory is only
 // streamed: the random accesses of the join all hit LDS.
+//
+// Latency hiding with one workgroup per CU: the first probe batch is loaded
+// while the build rows are inserted, and the hash chains of a thread's probe
+// rows are walked four at a time without branches, so that their LDS reads
+// are in flight together.
 #include "mdx.h"
 #include "mdx_internal.hpp"
 
 namespace mdx {
 namespace {
 
-constexpr uint32_t kNil = 0xffffffffu;
-constexpr uint16_t kNil16 = 0xffffu;
+// Chains end at the sentinel row kSent (one slot past the table), whose link
+// points to itself.
+constexpr uint32_t kSent = kJoinCap;
 constexpr int kJoinWaves = kJoinThreads / kWave;
-constexpr int kBuildBatch = 8;
+constexpr int kBuildBatch = 8;  // build rows per thread loaded together
 constexpr int kCells = kJoinRows * kJoinWaves;  // (row step, wave) partial sums
 constexpr int kCellsPerLane = kCells / kWave;
 static_assert(kCells % kWave == 0, "one wave scans the partial sums");
+static_assert(kSent <= 0xffffu, "chain links are 16-bit");
+constexpr int kWalk = 4;  // probe rows whose chains are walked together
+// Phase boundaries of a sub-bucket (0 ticket, 1 build, 2 count, 3 chained
+// scan, 4 emit); a timing build defines MDX_PHASE to record them.
+#ifndef MDX_PHASE
+#define MDX_PHASE(k)
+#endif
+static_assert(kJoinRows % kWalk == 0, "walk groups tile the thread's rows");
 
 // Chain bucket: hash bits 20..31, away from the partition's low bits and the
 // sub-bucket's top bits.
@@ -50,7 +64,7 @@ __global__ __launch_bounds__(kBlock) void rj_plan(const int64_t *__restrict__ su
         over |= (subL[s + 1] - subL[s]) > kJoinCap;
     }
     if (over)
-        *w.use = 0;  // any block may clear it; block 0 set it below first
+        *w.use = 0;  // rj_plan_init set it to 1 before this kernel
     if (blockIdx.x == 0 && threadIdx.x == 0)
         *w.ticket = 0;
 }
@@ -60,14 +74,10 @@ __global__ void rj_plan_init(RJoinWs w)
     *w.use = 1;
 }
 
-// Look up rows [rb, re) of the probe side (this thread's rows: rb + j * 1024
-// + tid): per row the number of matches (high 16 bits; at most kJoinCap) and
-// the first matching build row (low 16 bits).
+// This thread's rows of the batch starting at rb: rb + j * kJoinThreads + tid.
 template <typename K>
-__device__ __forceinline__ void lookup_batch(const K *__restrict__ rk, const int64_t *__restrict__ rv,
-                                             int64_t rb, int64_t re, bool any, const uint64_t *th,
-                                             const uint16_t *tn, const uint32_t *head, K *kk,
-                                             int64_t *vv, uint32_t *mf)
+__device__ __forceinline__ void load_batch(const K *__restrict__ rk, const int64_t *__restrict__ rv,
+                                           int64_t rb, int64_t re, K *kk, int64_t *vv)
 {
     const int tid = threadIdx.x;
 #pragma unroll
@@ -76,36 +86,77 @@ __device__ __forceinline__ void lookup_batch(const K *__restrict__ rk, const int
         kk[j] = r < re ? __builtin_nontemporal_load(rk + r) : K(0);
         vv[j] = r < re ? __builtin_nontemporal_load(rv + r) : 0;
     }
+}
+
+// Per row: the number of matches (high 16 bits; at most kJoinCap) and the
+// first matching build row in chain order (low 16 bits; meaningful when the
+// count is not 0).  The chains of kWalk rows are walked together without
+// branches: a finished chain sits on the sentinel row, whose link points to
+// itself, so every step issues all kWalk rows' LDS reads at once.
+template <typename K>
+__device__ __forceinline__ void match_batch(int64_t rb, int64_t re, bool any, const uint64_t *th,
+                                            const uint16_t *tn, const uint32_t *head, const K *kk,
+                                            uint32_t *mf)
+{
+    const int tid = threadIdx.x;
 #pragma unroll
-    for (int j = 0; j < kJoinRows; ++j) {
-        const int64_t r = rb + (int64_t)j * kJoinThreads + tid;
-        uint32_t cnt = 0, fst = kNil16;
-        if (any && r < re) {
-            const uint64_t h = fmix64(key_bits(kk[j]));
-            uint32_t e = head[bucket_of(h)];
-            while (e != kNil) {
-                if (th[e] == h) {
-                    if (cnt == 0)
-                        fst = e;
-                    ++cnt;
-                }
-                const uint16_t nx = tn[e];
-                e = nx == kNil16 ? kNil : (uint32_t)nx;
+    for (int g = 0; g < kJoinRows; g += kWalk) {
+        uint64_t h[kWalk];
+        uint32_t e[kWalk];
+        bool live = false;
+#pragma unroll
+        for (int i = 0; i < kWalk; ++i) {
+            const int j = g + i;
+            const int64_t r = rb + (int64_t)j * kJoinThreads + tid;
+            mf[j] = 0;
+            h[i] = fmix64(key_bits(kk[j]));
+            e[i] = (any && r < re) ? head[bucket_of(h[i])] : kSent;
+            live |= e[i] != kSent;
+        }
+        while (ballot(live)) {
+            uint64_t x[kWalk];
+            uint32_t nx[kWalk];
+#pragma unroll
+            for (int i = 0; i < kWalk; ++i) {
+                x[i] = th[e[i]];
+                nx[i] = tn[e[i]];
+            }
+            live = false;
+#pragma unroll
+            for (int i = 0; i < kWalk; ++i) {
+                const int j = g + i;
+                if (x[i] == h[i] && e[i] != kSent)
+                    mf[j] = mf[j] == 0 ? ((1u << 16) | e[i]) : mf[j] + (1u << 16);
+                e[i] = nx[i];
+                live |= e[i] != kSent;
             }
         }
-        mf[j] = (cnt << 16) | fst;
     }
 }
 
-// Per-(row step, wave) sums of m into cw (row order = step-major).
+// Per-(row step, wave) sums of the match counts into cw (row order =
+// step-major).  When no row of the step matches twice, the sum is a
+// population count.
 __device__ __forceinline__ void cell_sums(const uint32_t *mf, int64_t *cw, int lane, int wv)
 {
 #pragma unroll
     for (int j = 0; j < kJoinRows; ++j) {
-        const int64_t s = wave_sum((int64_t)(mf[j] >> 16));
+        const uint32_t cnt = mf[j] >> 16;
+        const uint64_t one = ballot(cnt == 1), many = ballot(cnt > 1);
+        const int64_t s = many ? wave_sum((int64_t)cnt) : (int64_t)__popcll(one);
         if (lane == 0)
             cw[j * kJoinWaves + wv] = s;
     }
+}
+
+// Wave 0: total of the cells.
+__device__ __forceinline__ int64_t cell_total(const int64_t *cw, int lane)
+{
+    int64_t loc = 0;
+#pragma unroll
+    for (int i = 0; i < kCellsPerLane; ++i)
+        loc += cw[lane * kCellsPerLane + i];
+    return wave_sum(loc);
 }
 
 // Wave 0: cw := exclusive prefix of cw (step-major), returns the total.
@@ -131,74 +182,92 @@ __device__ __forceinline__ int64_t cell_scan(int64_t *cw, int lane)
 // the batch's first match; cw holds the exclusive cell prefixes.
 template <typename K>
 __device__ __forceinline__ void emit_batch(const K *kk, const int64_t *vv, const uint32_t *mf,
-                                           const int64_t *cw, int64_t base,
-                                           const uint64_t *th, const int64_t *tp,
-                                           const uint16_t *tn, K *out_key, int64_t *out_l,
-                                           int64_t *out_r, int lane, int wv)
+                                           const int64_t *cw, int64_t base, const uint64_t *th,
+                                           const int64_t *tp, const uint16_t *tn, K *out_key,
+                                           int64_t *out_l, int64_t *out_r, int lane, int wv)
 {
 #pragma unroll
     for (int j = 0; j < kJoinRows; ++j) {
         const uint32_t cnt = mf[j] >> 16, fst = mf[j] & 0xffffu;
-        const int64_t inc = wave_incl_scan((int64_t)cnt, lane);
+        const uint64_t one = ballot(cnt == 1), many = ballot(cnt > 1);
+        const int64_t before =
+            many ? wave_incl_scan((int64_t)cnt, lane) - (int64_t)cnt : (int64_t)mbcnt(one);
         if (cnt == 0)
             continue;
-        int64_t at = base + cw[j * kJoinWaves + wv] + inc - (int64_t)cnt;
+        int64_t at = base + cw[j * kJoinWaves + wv] + before;
         if (cnt == 1) {
             out_key[at] = kk[j];
             out_l[at] = tp[fst];
             out_r[at] = vv[j];
         } else {
             const uint64_t h = fmix64(key_bits(kk[j]));
-            uint32_t e = fst;
-            while (e != kNil) {
+            for (uint32_t e = fst; e != kSent; e = tn[e]) {
                 if (th[e] == h) {
                     out_key[at] = kk[j];
                     out_l[at] = tp[e];
                     out_r[at] = vv[j];
                     ++at;
                 }
-                const uint16_t nx = tn[e];
-                e = nx == kNil16 ? kNil : (uint32_t)nx;
             }
         }
     }
 }
 
+// The kernel's kJoinPerCu workgroups of kJoinThreads fill a CU's 4 SIMDs
+// with kJoinSimdWaves waves each.
+constexpr int kJoinSimdWaves = kJoinPerCu * kJoinThreads / (4 * kWave);
 template <typename K>
-__global__ __launch_bounds__(kJoinThreads) void rj_join(
+__global__ __launch_bounds__(kJoinThreads)
+__attribute__((amdgpu_waves_per_eu(kJoinSimdWaves, kJoinSimdWaves))) void rj_join(
     const K *__restrict__ lk, const int64_t *__restrict__ lv, const int64_t *__restrict__ subL,
     const K *__restrict__ rk, const int64_t *__restrict__ rv, const int64_t *__restrict__ subR,
     RJoinWs w, ProbeOut o, int32_t *status)
 {
-    __shared__ uint64_t th[kJoinCap];     // hash of build row i
-    __shared__ int64_t tp[kJoinCap];      // payload of build row i
-    __shared__ uint16_t tn[kJoinCap];     // next row in i's chain
-    __shared__ uint32_t head[kJoinHeads]; // last row inserted per bucket
+    __shared__ uint64_t th[kJoinCap + 1];  // hash of build row i
+    __shared__ int64_t tp[kJoinCap];       // payload of build row i
+    __shared__ uint16_t tn[kJoinCap + 1];  // next row in i's chain
+    __shared__ uint32_t head[kJoinHeads];  // last row inserted per bucket
     __shared__ int64_t cw[kCells];
-    __shared__ int64_t s_sb, s_excl, s_total;
+    __shared__ int64_t s_next, s_excl, s_total;
 
     if (*w.use == 0)
         return;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
     K *out_key = (K *)o.key;
     const int64_t S = w.S;
+    if (tid == 0) {
+        th[kSent] = 0;
+        tn[kSent] = (uint16_t)kSent;
+    }
 
+    // Sub-buckets are taken strictly in ticket order, just before each is
+    // started: a ticket taken ahead of time would make later sub-buckets wait
+    // for it in the chained scan.
     for (;;) {
         if (tid == 0)
-            s_sb = (int64_t)atomicAdd(w.ticket, 1u);
+            s_next = (int64_t)atomicAdd(w.ticket, 1u);
         __syncthreads();
-        const int64_t s = s_sb;
+        const int64_t s = s_next;
+        __syncthreads();  // everyone has read s_next before it is replaced
         if (s >= S)
             break;
+        MDX_PHASE(0);
         const int64_t bL = subL[s], nb = subL[s + 1] - bL;  // nb <= kJoinCap (plan flag)
         const int64_t bR = subR[s], eR = subR[s + 1];
         const int64_t nbatch = (eR - bR + kJoinBatch - 1) / kJoinBatch;
         const bool any = nb > 0 && nbatch > 0;
 
-        // 1. build, kBuildBatch rows per thread at a time
+        // Build: insert the sub-bucket's rows into the LDS table, kBuildBatch
+        // rows per thread at a time; the first probe batch's loads are issued
+        // before the inserts.
+        K kk[kJoinRows];
+        int64_t vv[kJoinRows];
+        uint32_t mf[kJoinRows];
+        if (nbatch > 0)
+            load_batch(rk, rv, bR, eR, kk, vv);
         if (any) {
             for (int i = tid; i < kJoinHeads; i += kJoinThreads)
-                head[i] = kNil;
+                head[i] = kSent;
             __syncthreads();
             for (int base = 0; base < (int)nb; base += kBuildBatch * kJoinThreads) {
                 K bk[kBuildBatch];
@@ -223,21 +292,17 @@ __global__ __launch_bounds__(kJoinThreads) void rj_join(
             __syncthreads();
         }
 
-        // 2. count every probe row's matches
-        K kk[kJoinRows];
-        int64_t vv[kJoinRows];
-        uint32_t mf[kJoinRows];
+        MDX_PHASE(1);
+        // Count every probe row's matches.
         int64_t total = 0;
         for (int64_t b = 0; b < nbatch; ++b) {
-            lookup_batch(rk, rv, bR + b * kJoinBatch, eR, any, th, tn, head, kk, vv, mf);
+            if (b > 0)
+                load_batch(rk, rv, bR + b * kJoinBatch, eR, kk, vv);
+            match_batch(bR + b * kJoinBatch, eR, any, th, tn, head, kk, mf);
             cell_sums(mf, cw, lane, wv);
             __syncthreads();
             if (wv == 0) {
-                int64_t loc = 0;
-#pragma unroll
-                for (int i = 0; i < kCellsPerLane; ++i)
-                    loc += cw[lane * kCellsPerLane + i];
-                const int64_t all = wave_sum(loc);
+                const int64_t all = cell_total(cw, lane);
                 if (lane == 0)
                     s_total = all;
             }
@@ -245,7 +310,8 @@ __global__ __launch_bounds__(kJoinThreads) void rj_join(
             total += s_total;
         }
 
-        // chained scan over sub-buckets
+        MDX_PHASE(2);
+        // Chained scan over sub-buckets.
         if (wv == 0) {
             const int64_t ex = lookback(w.status, s, total, lane, status);
             if (lane == 0) {
@@ -255,8 +321,9 @@ __global__ __launch_bounds__(kJoinThreads) void rj_join(
         }
         __syncthreads();
         const int64_t E = s_excl;
+        MDX_PHASE(3);
 
-        // 3. write the output rows
+        // Write the output rows.
         if (E + total > o.cap) {
             if (tid == 0 && total > 0)
                 or_status(status, MDX_DEV_OUTPUT_OVERFLOW);
@@ -269,7 +336,8 @@ __global__ __launch_bounds__(kJoinThreads) void rj_join(
             } else {
                 int64_t run = E;
                 for (int64_t b = 0; b < nbatch; ++b) {
-                    lookup_batch(rk, rv, bR + b * kJoinBatch, eR, any, th, tn, head, kk, vv, mf);
+                    load_batch(rk, rv, bR + b * kJoinBatch, eR, kk, vv);
+                    match_batch(bR + b * kJoinBatch, eR, any, th, tn, head, kk, mf);
                     cell_sums(mf, cw, lane, wv);
                     __syncthreads();
                     if (wv == 0) {
@@ -285,6 +353,7 @@ __global__ __launch_bounds__(kJoinThreads) void rj_join(
             }
         }
         __syncthreads();  // the table is reused by the next sub-bucket
+        MDX_PHASE(4);
     }
 }
 
@@ -324,7 +393,8 @@ hipError_t launch_rjoin(const void *lk, const int64_t *lv, const int64_t *subL, 
 {
     (void)P;
     (void)qbits;
-    const int G = device_fill_blocks() / 8 > 0 ? device_fill_blocks() / 8 : 1;  // one per CU
+    const int cus = device_fill_blocks() / 8 > 0 ? device_fill_blocks() / 8 : 1;
+    const int G = cus * kJoinPerCu;  // all resident at once
     trace_begin("rj_join", s);
     if (key_bytes == 8)
         hipLaunchKernelGGL(rj_join<int64_t>, dim3(G), dim3(kJoinThreads), 0, s,
