@@ -96,6 +96,24 @@ def cpu_baseline(scale):
     }
 
 
+def copy_ceiling(torch, dev, n=1 << 27, reps=5):
+    """Device-to-device copy of n int64 (read n*8 + write n*8 bytes): the
+    achievable-bandwidth reference, and the known-size kernel that scales
+    the HBM byte counters of a counter run."""
+    src = torch.arange(n, dtype=torch.int64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"bytes": 2 * n * 8, "ms": round(ms, 4), "gbs": round(2 * n * 8 / (ms / 1e3) / 1e9, 1)}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -131,6 +149,9 @@ def main():
     def step():
         mdx.mdx_merge(lk, lv, rk, rv, P, out_capacity=cap, out=out, out_offsets=off, workspace=ws,
                       status=status, stream=stream)
+
+    copy = copy_ceiling(torch, dev)
+    log(f"plain copy of {copy['bytes'] >> 20} MiB: {copy['gbs']:.0f} GB/s (read + write)")
 
     log(f"warmup {args.warmup}")
     for _ in range(args.warmup):
@@ -216,6 +237,7 @@ def main():
                    "n_left": nl, "n_right": nr, "P": P, "output_rows": total},
         "roofline": roofline,
         "step_hbm_fraction": round(step_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "copy_ceiling": copy,
         "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in kernels.items()},
         "kernel_sources": kernel_sources_hash(),
     }

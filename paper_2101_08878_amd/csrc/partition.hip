@@ -247,8 +247,13 @@ __device__ __forceinline__ void scatter_tile(const K *__restrict__ keys,
     for (int s = tid; s < rows; s += kBlock) {
         const uint32_t p = stage_p[s];
         const int64_t dst = gbase[p] + (s - (int)tstart[p]);
-        __builtin_nontemporal_store(stage_k[s], keys_out + dst);
-        __builtin_nontemporal_store(stage_v[s], pay_out + dst);
+        // Ordinary stores: a run's first and last cache lines are shared
+        // with the neighbouring tiles' runs and must meet them in L2 (the
+        // XCD-contiguous tile order keeps those tiles on one L2).  With
+        // streaming stores the partial lines went to HBM separately: 25% more
+        // bytes written, 26% slower at a fan-out of 128.
+        keys_out[dst] = stage_k[s];
+        pay_out[dst] = stage_v[s];
     }
 }
 
