@@ -13,7 +13,7 @@ device memory before the timed region.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
-import hashlib
+import glob
 import json
 import os
 import sys
@@ -42,12 +42,18 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_sources_hash():
-    h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2101_08878_amd", "csrc"))):
-        with open(os.path.join(ROOT, "paper_2101_08878_amd", "csrc", f), "rb") as fh:
-            h.update(f.encode() + fh.read())
-    return h.hexdigest()[:16]
+def counted_traffic(kernel, workload, sources):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/*traffic.json, written by paper_2101_08878_amd.rocprof_summary
+    from FETCH_SIZE and WRITE_SIZE runs), or None when there is none for the
+    current kernel sources."""
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*traffic.json"))):
+        with open(f) as fh:
+            t = json.load(fh)
+        if t.get("kernel") == kernel and t.get("workload") == workload \
+                and t.get("kernel_sources") == sources:
+            return t["traffic_bytes_per_launch"], os.path.relpath(f, ROOT)
+    return None, None
 
 
 def algorithmic_bytes_per_step(kernel, nl, nr, key_bytes, total_out):
@@ -126,6 +132,7 @@ def main():
     import torch
 
     import paper_2101_08878_amd as mdx
+    from paper_2101_08878_amd.rocprof_summary import kernel_sources_hash
     from workloads import CONFIGS, config_inputs
 
     spec = CONFIGS[args.config]
@@ -213,9 +220,11 @@ def main():
     dtrace.close()
     bytes_per_launch = algorithmic_bytes_per_step(dom, nl, nr, key_bytes, total) / kd["launches_per_step"]
     achieved = bytes_per_launch / (kd["avg_launch_ms"] / 1e3) / 1e9
+    sources = kernel_sources_hash()
+    traffic, traffic_src = counted_traffic(dom, args.config, sources)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "bytes_per_launch": int(bytes_per_launch),
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "traffic_source": traffic_src, "bytes_per_launch": int(bytes_per_launch),
                 "avg_launch_us": round(kd["avg_launch_ms"] * 1e3, 2)}
     step_bytes = (nl + nr) * 2 * (key_bytes + 8) + (nl + nr) * (key_bytes + 8 + 16) \
         + total * (key_bytes + 16)
@@ -239,7 +248,7 @@ def main():
         "step_hbm_fraction": round(step_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "copy_ceiling": copy,
         "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in kernels.items()},
-        "kernel_sources": kernel_sources_hash(),
+        "kernel_sources": sources,
     }
     if args.cpu_baseline == "on":
         del lk, lv, rk, rv, ws, out
