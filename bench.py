@@ -35,7 +35,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="paper", choices=["paper", "plain"])
+    ap.add_argument("--config", default="paper", choices=["paper", "plain", "batched"])
+    ap.add_argument("--batch-count", type=int, default=4096,
+                    help="batched: number of merges (4096 = the full batch)")
+    ap.add_argument("--lanes", type=int, default=4, help="batched: concurrent lanes")
+    ap.add_argument("--graph-merges", type=int, default=256,
+                    help="batched: merges captured per HIP graph (graphs replay in order)")
     ap.add_argument("--cpu-baseline", default="on", choices=["on", "off"])
     ap.add_argument("--cpu-sample-scale", type=float, default=0.2,
                     help="fraction of the workload the oracle runs on the host")
@@ -120,6 +125,182 @@ def copy_ceiling(torch, dev, n=1 << 27, reps=5):
     return {"bytes": 2 * n * 8, "ms": round(ms, 4), "gbs": round(2 * n * 8 / (ms / 1e3) / 1e9, 1)}
 
 
+def batched_inputs(torch, specs, dev, seed=0, frac=0.3):
+    """The batch's tables, drawn on the device with torch's generator (the
+    host would need minutes for ~4E9 rows): per merge, left keys a random
+    permutation of [0, nL); right keys: round(frac nR) drawn from the left
+    keys, the rest uniform in [nL, 2 nL), shuffled; payload = row index.
+    The same recipe as workloads.match_fraction_tables, other random bits."""
+    import paper_2101_08878_amd as mdx
+    jobs, matched = [], []
+    g = torch.Generator(device=dev)
+    for s in specs:
+        g.manual_seed(seed * 1_000_003 + s.index)
+        kd = torch.int32 if s.key_dtype == "int32" else torch.int64
+        nl, nr = s.n_left, s.n_right
+        m = int(round(frac * nr))
+        kl = torch.randperm(nl, generator=g, device=dev, dtype=torch.int64)
+        hit = kl[torch.randint(0, nl, (m,), generator=g, device=dev, dtype=torch.int64)]
+        miss = torch.randint(nl, 2 * nl, (nr - m,), generator=g, device=dev, dtype=torch.int64)
+        kr = torch.cat([hit, miss])[torch.randperm(nr, generator=g, device=dev)]
+        jobs.append(mdx.MergeJob(kl.to(kd), torch.arange(nl, dtype=torch.int64, device=dev),
+                                 kr.to(kd).contiguous(), torch.arange(nr, dtype=torch.int64, device=dev),
+                                 8, max(m, 1)))
+        matched.append(m)
+    for j in jobs:
+        j.status = torch.zeros(1, dtype=torch.int32, device=dev)
+    return jobs, matched
+
+
+def batched_cpu_baseline(specs, budget_s=15.0):
+    """The oracle (one host thread) on the batch's first merges, drawn with
+    the workloads generator, until budget_s of oracle time is spent."""
+    import oracle
+    from workloads import batch_tables
+
+    rows, spent, k = 0, 0.0, 0
+    for s in specs:
+        kl, vl, kr, vr = batch_tables(s)
+        t0 = time.perf_counter()
+        oracle.hash_partition(kl, vl, 8)
+        oracle.hash_partition(kr, vr, 8)
+        oracle.join(kl, vl, kr, vr)
+        spent += time.perf_counter() - t0
+        rows += kl.size + kr.size
+        k += 1
+        if spent >= budget_s:
+            break
+    return {"value": rows / spent, "unit": "input rows/s", "cores": 1, "kind": "oracle",
+            "sample": f"the batch's first {k} merges ({rows} input rows), P=8: both partitions "
+                      f"+ sort-merge join, {spent:.2f} s on one host thread"}
+
+
+def run_batched(args):
+    """Secondary line: a batch of uneven merges (sizes log-uniform in
+    [1E3, 4E6] rows per side, int32 or int64 keys, match fraction 0.3, P=8),
+    one merge at a time vs mdx_merge_batch (eager, and replayed from a HIP
+    graph).  Inputs resident in HBM; every merge's |J| is checked."""
+    import torch
+
+    import paper_2101_08878_amd as mdx
+    from workloads import batch_specs
+
+    specs = batch_specs(4096)[: args.batch_count]
+    dev = torch.device("cuda:0")
+    log(f"batched: generating {len(specs)} merges on the device")
+    jobs, matched = batched_inputs(torch, specs, dev)
+    rows = sum(s.n_left + s.n_right for s in specs)
+    for j in jobs:
+        j.out = tuple(torch.empty(j.out_capacity, dtype=t, device=dev)
+                      for t in (j.left_keys.dtype, torch.int64, torch.int64))
+        j.out_offsets = torch.empty(j.P + 1, dtype=torch.int64, device=dev)
+    lanes = args.lanes
+    chunks = [jobs[i:i + args.graph_merges] for i in range(0, len(jobs), args.graph_merges)]
+    ws = torch.empty(max([mdx.mdx_merge_batch_workspace_bytes(jobs, lanes)] +
+                         [mdx.mdx_merge_batch_workspace_bytes(c, lanes) for c in chunks]),
+                     dtype=torch.uint8, device=dev)
+    big = max(jobs, key=lambda j: mdx.mdx_merge_workspace_bytes(
+        j.left_keys.numel(), j.right_keys.numel(), j.P, 4 if j.left_keys.dtype == torch.int32 else 8))
+    ws1 = torch.empty(mdx.mdx_merge_workspace_bytes(
+        big.left_keys.numel(), big.right_keys.numel(), big.P,
+        4 if big.left_keys.dtype == torch.int32 else 8), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.Stream(device=dev)
+    torch.cuda.synchronize()  # inputs were drawn on torch's current stream
+    log(f"batched: {rows} input rows, workspace {ws.numel() / 1e9:.2f} GB ({lanes} lanes)")
+
+    def sequential():
+        for j in jobs:
+            mdx.mdx_merge(j.left_keys, j.left_payload, j.right_keys, j.right_payload, j.P,
+                          out_capacity=j.out_capacity, out=j.out, out_offsets=j.out_offsets,
+                          workspace=ws1, status=j.status, stream=stream)
+
+    def batch():
+        mdx.mdx_merge_batch(jobs, lanes=lanes, workspace=ws, stream=stream)
+
+    def check(label):
+        tot = torch.stack([j.out_offsets[-1] for j in jobs]).cpu().tolist()
+        st = torch.cat([j.status for j in jobs]).cpu().tolist()
+        bad = [i for i in range(len(jobs)) if tot[i] != matched[i] or st[i] != 0]
+        if bad:
+            raise SystemExit(f"{label}: merge {bad[0]} gave |J|={tot[bad[0]]}, status {st[bad[0]]}, "
+                             f"want {matched[bad[0]]}")
+
+    def timed(fn, reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, (time.perf_counter() - w0) * 1e3 / reps
+
+    res = {}
+    for label, fn in [("one merge at a time", sequential), (f"batch, {lanes} lanes", batch)]:
+        for _ in range(max(args.warmup, 1)):
+            fn()
+        torch.cuda.synchronize()
+        check(label)
+        ms, wall = timed(fn, args.steps)
+        res[label] = (ms, wall)
+        log(f"  {label}: {ms:.2f} ms device, {wall:.2f} ms wall, {rows / (wall / 1e3):.4g} rows/s")
+    # the batch captured as graphs of graph_merges merges each (one
+    # workspace: the graphs replay one after another on `stream`)
+    graphs = []
+    for c in chunks:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            mdx.mdx_merge_batch(c, lanes=lanes, workspace=ws, stream=stream)
+        graphs.append(g)
+    torch.cuda.synchronize()
+
+    def replay():
+        with torch.cuda.stream(stream):
+            for g in graphs:
+                g.replay()
+
+    for j in jobs:
+        j.out_offsets.fill_(-1)
+    replay()
+    torch.cuda.synchronize()
+    check("graph")
+    ms, wall = timed(replay, args.steps)
+    res["graph"] = (ms, wall)
+    log(f"  batch in {len(graphs)} HIP graphs: {ms:.2f} ms device, {wall:.2f} ms wall, "
+        f"{rows / (wall / 1e3):.4g} rows/s")
+    seq_wall = res["one merge at a time"][1]
+    step_bytes = sum((s.n_left + s.n_right) * (2 * (4 if s.key_dtype == "int32" else 8) + 16)
+                     + (s.n_left + s.n_right) * ((4 if s.key_dtype == "int32" else 8) + 8 + 16)
+                     for s in specs) + sum(m * ((4 if s.key_dtype == "int32" else 8) + 16)
+                                           for s, m in zip(specs, matched))
+    achieved = step_bytes / (wall / 1e3) / 1e9
+    line = {
+        "metric": "input rows/s for a batch of 4096 uneven merges (1E3-4E6 rows per side, "
+                  "int32/int64 keys, P=8)",
+        "value": round(rows / (wall / 1e3), 1),
+        "unit": "input rows/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32/int64", "data": "synthetic",
+        "config": {"workload": f"batched: {len(specs)} merges, {rows} input rows, P=8, "
+                               f"match fraction 0.3, {lanes} lanes, replayed from HIP graphs of "
+                               f"{args.graph_merges} merges",
+                   "merges": len(specs), "input_rows": rows, "lanes": lanes,
+                   "graph_merges": args.graph_merges},
+        "roofline": {"bound": "hbm", "kernel": "whole batch", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None},
+        "modes_ms": {k: {"device": round(v[0], 3), "wall": round(v[1], 3)} for k, v in res.items()},
+        "speedup_vs_one_at_a_time": round(seq_wall / wall, 3),
+    }
+    if args.cpu_baseline == "on":
+        del jobs, ws, ws1
+        line["cpu_baseline"] = batched_cpu_baseline(specs)
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -128,6 +309,10 @@ def main():
               "(the exchange between workers is out of scope); run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.config == "batched":
+        run_batched(args)
+        return
 
     import torch
 

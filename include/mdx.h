@@ -56,7 +56,7 @@
 extern "C" {
 #endif
 
-#define MDX_ABI_VERSION 1
+#define MDX_ABI_VERSION 2
 
 /* Largest number of partitions (destinations). */
 #define MDX_MAX_P 4096
@@ -217,6 +217,61 @@ int32_t mdx_merge(const void *d_left_keys, const int64_t *d_left_payload, int64_
                   int32_t key_type, int32_t P, void *d_ws, size_t ws_bytes, void *d_out_key,
                   int64_t *d_out_lpay, int64_t *d_out_rpay, int64_t out_capacity,
                   int64_t *d_out_offsets, int32_t *d_status, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched merges: many independent merges in one call.
+ *
+ * A worker of the paper's benchmark merges every frame it holds (Section
+ * V-B); a service that answers many merge requests has many such merges at
+ * once, most of them small.  One small merge alone leaves the device idle
+ * between its dependent launches; a batch keeps several in flight.
+ *
+ * Merge i of h_descs[0..count) computes exactly what mdx_merge computes
+ * with the same arguments (same output rows, same offsets, same device
+ * status bits); merges are independent and may differ in sizes, key type
+ * and P.  The merges run on up to `lanes` concurrent lanes: HIP streams the
+ * library creates at the default priority on first use on a device and
+ * keeps until the process ends.  The lanes are forked from `stream` and
+ * joined back to it with events, so the batch is ordered on `stream` like a
+ * single call and can be captured into a HIP graph.  Merges are assigned
+ * largest first (by n_left + n_right), each to the lane with the fewest rows
+ * so far (ties: the lowest lane); a lane runs its merges one after another
+ * in its own slice of d_ws, sized for its largest merge.  With lanes = 1,
+ * or a single merge, everything runs on `stream` itself.
+ *
+ * h_descs: host array, read during the call only.  lanes: 1..MDX_MAX_LANES.
+ * d_ws: at least mdx_merge_batch_workspace_bytes(count, h_descs, lanes)
+ * bytes (depends on the sizes, key types and P of the merges only).
+ * Errors: MDX_ERR_INVALID for count < 0, a null h_descs with count > 0,
+ * lanes out of range, or any descriptor mdx_merge would reject (the
+ * message names the merge's index); MDX_ERR_WORKSPACE for a short
+ * workspace.  Nothing is enqueued on an error.  Outputs of different merges
+ * must not overlap one another.
+ * ------------------------------------------------------------------------- */
+#define MDX_MAX_LANES 8
+
+typedef struct mdx_merge_desc {
+    const void *d_left_keys;        /* [n_left] build keys, key_type */
+    const int64_t *d_left_payload;  /* [n_left] */
+    int64_t n_left;
+    const void *d_right_keys;       /* [n_right] probe keys, key_type */
+    const int64_t *d_right_payload; /* [n_right] */
+    int64_t n_right;
+    int32_t key_type; /* MDX_KEY_I32 or MDX_KEY_I64, both tables */
+    int32_t P;        /* partitions, 1..MDX_MAX_P */
+    void *d_out_key;  /* [out_capacity] output columns, as mdx_merge */
+    int64_t *d_out_lpay;
+    int64_t *d_out_rpay;
+    int64_t out_capacity;
+    int64_t *d_out_offsets; /* [P+1] */
+    int32_t *d_status;      /* may be NULL; may be shared by merges */
+} mdx_merge_desc;
+
+int32_t mdx_merge_batch_workspace_bytes(int32_t count, const mdx_merge_desc *h_descs,
+                                        int32_t lanes, size_t *h_bytes);
+
+int32_t mdx_merge_batch(int32_t count, const mdx_merge_desc *h_descs, int32_t lanes, void *d_ws,
+                        size_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Kernel timing for benchmarks.

@@ -36,6 +36,7 @@ MDX_DEV_OUTPUT_OVERFLOW = 1
 MDX_DEV_BAD_PARTITIONING = 2
 MDX_DEV_SCAN_TIMEOUT = 4
 MDX_MAX_P = 4096
+MDX_MAX_LANES = 8
 
 _i32, _i64, _sz, _vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p
 
@@ -46,6 +47,16 @@ class mdx_table(ctypes.Structure):
         ("n", _i64), ("d_mem", _vp), ("bytes", _sz),
         ("d_offsets", _vp), ("d_flags", _vp), ("d_bump", _vp),
         ("d_slots", _vp), ("d_gstart", _vp), ("d_grouped", _vp),
+    ]
+
+
+class mdx_merge_desc(ctypes.Structure):
+    _fields_ = [
+        ("d_left_keys", _vp), ("d_left_payload", _vp), ("n_left", _i64),
+        ("d_right_keys", _vp), ("d_right_payload", _vp), ("n_right", _i64),
+        ("key_type", _i32), ("P", _i32),
+        ("d_out_key", _vp), ("d_out_lpay", _vp), ("d_out_rpay", _vp), ("out_capacity", _i64),
+        ("d_out_offsets", _vp), ("d_status", _vp),
     ]
 
 
@@ -71,6 +82,10 @@ _merge_ws = _sig("mdx_merge_workspace_bytes", _i32, _i64, _i64, _i32, _i32, ctyp
 _merge = _sig("mdx_merge", _i32, _vp, _vp, _i64, _vp, _vp, _i64, _i32, _i32, _vp, _sz,
               _vp, _vp, _vp, _i64, _vp, _vp, _vp)
 
+_batch_ws = _sig("mdx_merge_batch_workspace_bytes", _i32, _i32, ctypes.POINTER(mdx_merge_desc), _i32,
+                 ctypes.POINTER(_sz))
+_batch = _sig("mdx_merge_batch", _i32, _i32, ctypes.POINTER(mdx_merge_desc), _i32, _vp, _sz, _vp)
+
 _trace = _sig("mdx_trace_kernel", _i32, ctypes.c_char_p, _vp, _vp, _i32, ctypes.POINTER(_i32))
 
 ABI_FUNCTIONS = [
@@ -79,6 +94,7 @@ ABI_FUNCTIONS = [
     "mdx_join_table_bytes", "mdx_join_build",
     "mdx_join_probe_workspace_bytes", "mdx_join_probe",
     "mdx_merge_workspace_bytes", "mdx_merge",
+    "mdx_merge_batch_workspace_bytes", "mdx_merge_batch",
     "mdx_trace_kernel",
 ]
 TRACEABLE_KERNELS = ["part_hist", "part_scatter", "seg_scatter", "rj_join", "tbl_init",
@@ -294,6 +310,69 @@ def merge(left_keys, left_payload, right_keys, right_payload, P: int, *, capacit
             return ok[:total], ol[:total], orr[:total], off
         cap = total
     raise MdxError(MDX_ERR_INVALID, "output capacity retry failed")
+
+
+# ---- batched merges ---------------------------------------------------------------------
+
+@dataclass
+class MergeJob:
+    """One merge of a batch: mdx_merge's inputs and (optionally) outputs."""
+    left_keys: torch.Tensor
+    left_payload: torch.Tensor
+    right_keys: torch.Tensor
+    right_payload: torch.Tensor
+    P: int
+    out_capacity: int
+    out: tuple | None = None
+    out_offsets: torch.Tensor | None = None
+    status: torch.Tensor | None = None
+
+
+def _batch_descs(jobs, with_pointers: bool):
+    descs = (mdx_merge_desc * max(len(jobs), 1))()
+    for i, j in enumerate(jobs):
+        d = descs[i]
+        if j.right_keys.dtype != j.left_keys.dtype:
+            raise TypeError(f"merge {i}: left and right keys must have the same dtype")
+        d.n_left, d.n_right = j.left_keys.numel(), j.right_keys.numel()
+        d.key_type, d.P, d.out_capacity = _key_type(j.left_keys), int(j.P), int(j.out_capacity)
+        if with_pointers:
+            nl, nr, cap, kd = d.n_left, d.n_right, d.out_capacity, j.left_keys.dtype
+            d.d_left_keys = _dev(j.left_keys, "left_keys")
+            d.d_left_payload = _dev(j.left_payload, "left_payload", torch.int64, nl)
+            d.d_right_keys = _dev(j.right_keys, "right_keys")
+            d.d_right_payload = _dev(j.right_payload, "right_payload", torch.int64, nr)
+            d.d_out_key = _dev(j.out[0], "out_key", kd, cap)
+            d.d_out_lpay = _dev(j.out[1], "out_lpay", torch.int64, cap)
+            d.d_out_rpay = _dev(j.out[2], "out_rpay", torch.int64, cap)
+            d.d_out_offsets = _dev(j.out_offsets, "out_offsets", torch.int64, j.P + 1)
+            d.d_status = _dev(j.status, "status", torch.int32, 1) if j.status is not None else None
+    return descs
+
+
+def mdx_merge_batch_workspace_bytes(jobs, lanes: int) -> int:
+    """Workspace bytes of mdx_merge_batch for these jobs (sizes only)."""
+    return _bytes(_batch_ws, len(jobs), _batch_descs(jobs, False), int(lanes))
+
+
+def mdx_merge_batch(jobs, *, lanes: int = 4, workspace=None, stream=None):
+    """Run every MergeJob as mdx_merge would, on up to `lanes` concurrent
+    lanes.  Missing outputs are allocated here.  Asynchronous; returns the
+    jobs with their outputs filled in."""
+    for j in jobs:
+        dev = j.left_keys.device
+        if j.out is None:
+            j.out = _outputs(j.out_capacity, j.left_keys.dtype, dev, None)
+        if j.out_offsets is None:
+            j.out_offsets = torch.empty(j.P + 1, dtype=torch.int64, device=dev)
+    if workspace is None:
+        need = mdx_merge_batch_workspace_bytes(jobs, lanes)
+        dev = jobs[0].left_keys.device if jobs else torch.device("cuda")
+        workspace = _workspace(need, dev)
+    descs = _batch_descs(jobs, True)
+    _check(_batch(len(jobs), descs, int(lanes), _dev(workspace, "workspace"),
+                  workspace.numel() * workspace.element_size(), _stream(stream)))
+    return jobs
 
 
 # ---- kernel tracing (benchmarks) -------------------------------------------------------

@@ -1,8 +1,11 @@
 // The extern "C" entry points of libmdx: argument validation (pure host code,
 // before anything is enqueued), workspace and table carving, and the order of
 // kernel launches.  No device memory is allocated here.
+#include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "mdx.h"
 #include "mdx_internal.hpp"
@@ -508,55 +511,63 @@ int32_t mdx_merge_workspace_bytes(int64_t n_left, int64_t n_right, int32_t P, in
     return MDX_OK;
 }
 
-int32_t mdx_merge(const void *d_left_keys, const int64_t *d_left_payload, int64_t n_left,
-                  const void *d_right_keys, const int64_t *d_right_payload, int64_t n_right,
-                  int32_t key_type, int32_t P, void *d_ws, size_t ws_bytes, void *d_out_key,
-                  int64_t *d_out_lpay, int64_t *d_out_rpay, int64_t out_capacity,
-                  int64_t *d_out_offsets, int32_t *d_status, hipStream_t stream)
+// Host checks of one merge's arguments (W names the caller in messages).
+static int32_t check_merge(const mdx_merge_desc &d, const char *W)
 {
-    g_err.clear();
-    const char *W = "mdx_merge";
-    if (int32_t e = check_sizes(n_left, P, key_type, W))
+    if (int32_t e = check_sizes(d.n_left, d.P, d.key_type, W))
         return e;
-    if (int32_t e = check_sizes(n_right, P, key_type, W))
+    if (int32_t e = check_sizes(d.n_right, d.P, d.key_type, W))
         return e;
-    if (int32_t e = check_columns(d_left_keys, d_left_payload, n_left, key_type, W))
+    if (int32_t e = check_columns(d.d_left_keys, d.d_left_payload, d.n_left, d.key_type, W))
         return e;
-    if (int32_t e = check_columns(d_right_keys, d_right_payload, n_right, key_type, W))
+    if (int32_t e = check_columns(d.d_right_keys, d.d_right_payload, d.n_right, d.key_type, W))
         return e;
-    if (int32_t e = check_outputs(d_out_key, d_out_lpay, d_out_rpay, out_capacity, key_type,
-                                  d_out_offsets, d_status, W))
-        return e;
-    const MergeLayout M = merge_layout(n_left, n_right, P, key_type);
-    if (!d_ws || !aligned(d_ws, kAlign))
-        return fail(MDX_ERR_INVALID, "mdx_merge: workspace null or not 256-byte aligned");
-    if (ws_bytes < M.bytes)
-        return fail(MDX_ERR_WORKSPACE,
-                    "mdx_merge: workspace needs " + std::to_string(M.bytes) + " bytes");
-    const size_t ob = (size_t)out_capacity * 8;
-    if (overlap(d_ws, ws_bytes, d_out_key, (size_t)out_capacity * key_type) ||
-        overlap(d_ws, ws_bytes, d_out_lpay, ob) || overlap(d_ws, ws_bytes, d_out_rpay, ob))
-        return fail(MDX_ERR_INVALID, "mdx_merge: workspace overlaps the output");
+    return check_outputs(d.d_out_key, d.d_out_lpay, d.d_out_rpay, d.out_capacity, d.key_type,
+                         d.d_out_offsets, d.d_status, W);
+}
 
+// Checks of a merge's workspace [ws, ws + ws_bytes) against its layout.
+static int32_t check_merge_ws(const mdx_merge_desc &d, const void *ws, size_t ws_bytes,
+                              size_t need, const char *W)
+{
+    if (!ws || !aligned(ws, kAlign))
+        return fail(MDX_ERR_INVALID, std::string(W) + ": workspace null or not 256-byte aligned");
+    if (ws_bytes < need)
+        return fail(MDX_ERR_WORKSPACE,
+                    std::string(W) + ": workspace needs " + std::to_string(need) + " bytes");
+    const size_t ob = (size_t)d.out_capacity * 8;
+    if (overlap(ws, ws_bytes, d.d_out_key, (size_t)d.out_capacity * d.key_type) ||
+        overlap(ws, ws_bytes, d.d_out_lpay, ob) || overlap(ws, ws_bytes, d.d_out_rpay, ob))
+        return fail(MDX_ERR_INVALID, std::string(W) + ": workspace overlaps the output");
+    return MDX_OK;
+}
+
+// Enqueue one checked merge on `stream`, workspace at d_ws.
+static hipError_t enqueue_merge(const mdx_merge_desc &d, void *d_ws, hipStream_t stream)
+{
+    const int32_t P = d.P, key_type = d.key_type;
+    const int64_t n_left = d.n_left, n_right = d.n_right;
+    const MergeLayout M = merge_layout(n_left, n_right, P, key_type);
     char *b = (char *)d_ws;
     const MergePlan &pl = M.plan;
     const int nA = (int)M.nA;
     void *lk1 = b + M.lk1_off, *rk1 = b + M.rk1_off;
     int64_t *lv1 = (int64_t *)(b + M.lv1_off), *rv1 = (int64_t *)(b + M.rv1_off);
     int64_t *offAL = (int64_t *)(b + M.offAL_off), *offAR = (int64_t *)(b + M.offAR_off);
+    int32_t *d_status = d.d_status;
     ProbeOut o;
-    o.key = d_out_key;
-    o.lpay = d_out_lpay;
-    o.rpay = d_out_rpay;
-    o.cap = out_capacity;
-    o.offsets = d_out_offsets;
+    o.key = d.d_out_key;
+    o.lpay = d.d_out_lpay;
+    o.rpay = d.d_out_rpay;
+    o.cap = d.out_capacity;
+    o.offsets = d.d_out_offsets;
 
     // 1. partition both tables by (partition, top q1bits of the hash)
-    hipError_t e = launch_partition(d_left_keys, d_left_payload, n_left, key_type, P, pl.q1bits,
-                                    lk1, lv1, offAL, b + M.partL_off, stream);
+    hipError_t e = launch_partition(d.d_left_keys, d.d_left_payload, n_left, key_type, P,
+                                    pl.q1bits, lk1, lv1, offAL, b + M.partL_off, stream);
     if (e == hipSuccess)
-        e = launch_partition(d_right_keys, d_right_payload, n_right, key_type, P, pl.q1bits, rk1,
-                             rv1, offAR, b + M.partR_off, stream);
+        e = launch_partition(d.d_right_keys, d.d_right_payload, n_right, key_type, P, pl.q1bits,
+                             rk1, rv1, offAR, b + M.partR_off, stream);
 
     // 2. split every first-pass bucket by the next q2bits: sub-buckets
     const void *lk = lk1, *rk = rk1;
@@ -590,7 +601,10 @@ int32_t mdx_merge(const void *d_left_keys, const int64_t *d_left_payload, int64_
 
     // 4. otherwise (a sub-bucket too large for LDS: heavy key repetition),
     // the global-table join over the first-pass output; its kernels do
-    // nothing when the radix join ran.
+    // nothing when the radix join ran.  No sub-bucket can exceed the table
+    // when the whole build side fits it: then they are not launched.
+    if (n_left <= kJoinCap)
+        return e;
     int64_t *offPL = (int64_t *)(b + M.offPL_off), *offPR = (int64_t *)(b + M.offPR_off);
     mdx_table t = carve_table(b + M.table_off, M.tl.bytes, n_left, P, key_type);
     const ProbeWs w = probe_ws(b + M.probe_off, M.ql);
@@ -610,6 +624,211 @@ int32_t mdx_merge(const void *d_left_keys, const int64_t *d_left_payload, int64_
         e = launch_probe_group(rk1, rv1, key_type, P, v, 0, w, o, d_status, stream);
     if (e == hipSuccess)
         e = launch_probe_finalize(P, w, o, jw.use, stream);
+    return e;
+}
+
+int32_t mdx_merge(const void *d_left_keys, const int64_t *d_left_payload, int64_t n_left,
+                  const void *d_right_keys, const int64_t *d_right_payload, int64_t n_right,
+                  int32_t key_type, int32_t P, void *d_ws, size_t ws_bytes, void *d_out_key,
+                  int64_t *d_out_lpay, int64_t *d_out_rpay, int64_t out_capacity,
+                  int64_t *d_out_offsets, int32_t *d_status, hipStream_t stream)
+{
+    g_err.clear();
+    const char *W = "mdx_merge";
+    const mdx_merge_desc d = {d_left_keys,   d_left_payload, n_left,       d_right_keys,
+                              d_right_payload, n_right,      key_type,     P,
+                              d_out_key,     d_out_lpay,     d_out_rpay,   out_capacity,
+                              d_out_offsets, d_status};
+    if (int32_t e = check_merge(d, W))
+        return e;
+    if (int32_t e = check_merge_ws(d, d_ws, ws_bytes, merge_layout(n_left, n_right, P, key_type).bytes, W))
+        return e;
+    const hipError_t e = enqueue_merge(d, d_ws, stream);
+    return e == hipSuccess ? MDX_OK : hip_fail(e, W);
+}
+
+// ---- batched merges ----------------------------------------------------------------
+
+}  // extern "C"
+
+namespace {
+
+// Lane of every merge (largest first, each to the lane with the fewest rows
+// so far; ties to the lowest lane), the order merges are enqueued in, and
+// every lane's workspace slice (sized for its largest merge).
+struct BatchPlan {
+    std::vector<int32_t> order, lane;
+    std::vector<size_t> lane_off;
+    int32_t used = 0;
+    size_t bytes = 0;
+};
+
+BatchPlan batch_plan(int32_t count, const mdx_merge_desc *h, int32_t lanes)
+{
+    BatchPlan B;
+    B.order.resize((size_t)count);
+    B.lane.assign((size_t)count, 0);
+    for (int32_t i = 0; i < count; ++i)
+        B.order[(size_t)i] = i;
+    std::stable_sort(B.order.begin(), B.order.end(), [&](int32_t a, int32_t b) {
+        return h[a].n_left + h[a].n_right > h[b].n_left + h[b].n_right;
+    });
+    const int32_t L = count < lanes ? (count > 0 ? count : 1) : lanes;
+    std::vector<int64_t> load((size_t)L, 0);
+    std::vector<size_t> need((size_t)L, 0);
+    for (int32_t i : B.order) {
+        int32_t l = 0;
+        for (int32_t k = 1; k < L; ++k)
+            if (load[(size_t)k] < load[(size_t)l])
+                l = k;
+        B.lane[(size_t)i] = l;
+        load[(size_t)l] += h[i].n_left + h[i].n_right;
+        const size_t b = merge_layout(h[i].n_left, h[i].n_right, h[i].P, h[i].key_type).bytes;
+        need[(size_t)l] = need[(size_t)l] > b ? need[(size_t)l] : b;
+    }
+    B.used = L;
+    B.lane_off.resize((size_t)L);
+    size_t o = 0;
+    for (int32_t l = 0; l < L; ++l) {
+        B.lane_off[(size_t)l] = o;
+        o += align_up(need[(size_t)l]);
+    }
+    B.bytes = o;
+    return B;
+}
+
+// Lane streams: created once per device, kept until the process ends.
+std::mutex g_lane_mu;
+std::vector<std::vector<hipStream_t>> g_lane_streams;
+
+hipError_t lane_streams(int32_t n, hipStream_t *out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    std::lock_guard<std::mutex> lock(g_lane_mu);
+    if ((int)g_lane_streams.size() <= dev)
+        g_lane_streams.resize((size_t)dev + 1);
+    auto &v = g_lane_streams[(size_t)dev];
+    while ((int32_t)v.size() < n) {
+        hipStream_t s;
+        e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+        if (e != hipSuccess)
+            return e;
+        v.push_back(s);
+    }
+    for (int32_t l = 0; l < n; ++l)
+        out[l] = v[(size_t)l];
+    return hipSuccess;
+}
+
+int32_t check_batch(int32_t count, const mdx_merge_desc *h, int32_t lanes, const char *W)
+{
+    if (count < 0)
+        return fail(MDX_ERR_INVALID, std::string(W) + ": count < 0");
+    if (count > 0 && !h)
+        return fail(MDX_ERR_INVALID, std::string(W) + ": h_descs is null");
+    if (lanes < 1 || lanes > MDX_MAX_LANES)
+        return fail(MDX_ERR_INVALID, std::string(W) + ": lanes outside [1, MDX_MAX_LANES]");
+    for (int32_t i = 0; i < count; ++i) {
+        const std::string Wi = std::string(W) + " (merge " + std::to_string(i) + ")";
+        if (int32_t e = check_sizes(h[i].n_left, h[i].P, h[i].key_type, Wi.c_str()))
+            return e;
+        if (int32_t e = check_sizes(h[i].n_right, h[i].P, h[i].key_type, Wi.c_str()))
+            return e;
+    }
+    return MDX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t mdx_merge_batch_workspace_bytes(int32_t count, const mdx_merge_desc *h_descs,
+                                        int32_t lanes, size_t *h_bytes)
+{
+    g_err.clear();
+    const char *W = "mdx_merge_batch_workspace_bytes";
+    if (int32_t e = check_batch(count, h_descs, lanes, W))
+        return e;
+    if (!h_bytes)
+        return fail(MDX_ERR_INVALID, std::string(W) + ": h_bytes is null");
+    *h_bytes = batch_plan(count, h_descs, lanes).bytes;
+    return MDX_OK;
+}
+
+int32_t mdx_merge_batch(int32_t count, const mdx_merge_desc *h_descs, int32_t lanes, void *d_ws,
+                        size_t ws_bytes, hipStream_t stream)
+{
+    g_err.clear();
+    const char *W = "mdx_merge_batch";
+    if (int32_t e = check_batch(count, h_descs, lanes, W))
+        return e;
+    const BatchPlan B = batch_plan(count, h_descs, lanes);
+    if (count > 0 && (!d_ws || !aligned(d_ws, kAlign)))
+        return fail(MDX_ERR_INVALID, std::string(W) + ": workspace null or not 256-byte aligned");
+    if (ws_bytes < B.bytes)
+        return fail(MDX_ERR_WORKSPACE,
+                    std::string(W) + ": workspace needs " + std::to_string(B.bytes) + " bytes");
+    for (int32_t i = 0; i < count; ++i) {
+        const mdx_merge_desc &d = h_descs[i];
+        const std::string Wi = std::string(W) + " (merge " + std::to_string(i) + ")";
+        if (int32_t e = check_merge(d, Wi.c_str()))
+            return e;
+        // its lane's slice holds its layout; its output stays clear of the
+        // whole batch workspace
+        const size_t need = merge_layout(d.n_left, d.n_right, d.P, d.key_type).bytes;
+        if (int32_t e = check_merge_ws(d, (char *)d_ws + B.lane_off[(size_t)B.lane[(size_t)i]],
+                                       need, need, Wi.c_str()))
+            return e;
+        if (int32_t e = check_merge_ws(d, d_ws, B.bytes, 0, Wi.c_str()))
+            return e;
+    }
+    if (count == 0)
+        return MDX_OK;
+
+    // One lane: the caller's stream itself.  Otherwise fork the lanes from
+    // `stream` and join them back with events.
+    hipStream_t ls[MDX_MAX_LANES];
+    hipError_t e = hipSuccess;
+    if (B.used == 1) {
+        ls[0] = stream;
+    } else {
+        e = lane_streams(B.used, ls);
+        if (e != hipSuccess)
+            return hip_fail(e, W);
+    }
+    hipEvent_t fork = nullptr, join[MDX_MAX_LANES] = {};
+    if (B.used > 1) {
+        e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = hipEventRecord(fork, stream);
+        for (int32_t l = 0; l < B.used && e == hipSuccess; ++l)
+            e = hipStreamWaitEvent(ls[l], fork, 0);
+    }
+    for (size_t k = 0; k < B.order.size() && e == hipSuccess; ++k) {
+        const int32_t i = B.order[k], l = B.lane[(size_t)i];
+        e = enqueue_merge(h_descs[i], (char *)d_ws + B.lane_off[(size_t)l], ls[l]);
+    }
+    if (B.used > 1) {
+        // join every lane that was forked, even after an error, so that
+        // `stream` never runs ahead of work already enqueued on a lane
+        for (int32_t l = 0; l < B.used; ++l) {
+            hipError_t e2 = hipEventCreateWithFlags(&join[l], hipEventDisableTiming);
+            if (e2 == hipSuccess)
+                e2 = hipEventRecord(join[l], ls[l]);
+            if (e2 == hipSuccess)
+                e2 = hipStreamWaitEvent(stream, join[l], 0);
+            if (e == hipSuccess)
+                e = e2;
+        }
+        for (int32_t l = 0; l < B.used; ++l)
+            if (join[l])
+                (void)hipEventDestroy(join[l]);
+        if (fork)
+            (void)hipEventDestroy(fork);
+    }
     return e == hipSuccess ? MDX_OK : hip_fail(e, W);
 }
 

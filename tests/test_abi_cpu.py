@@ -130,3 +130,72 @@ def test_build_probe_merge_validation():
     assert L._merge(*bad) == mdx.MDX_ERR_WORKSPACE
     bad = list(args); bad[2] = -3
     assert L._merge(*bad) == mdx.MDX_ERR_INVALID
+
+
+def test_merge_desc_struct_layout():
+    # 6 pointers/int64, 2 int32, 6 pointers/int64 on LP64, in the header's order
+    assert ctypes.sizeof(L.mdx_merge_desc) == 6 * 8 + 2 * 4 + 6 * 8
+    names = re.findall(r"^\s+[\w\s\*]*?\b(\w+);", _header().split("typedef struct mdx_merge_desc")[1]
+                       .split("} mdx_merge_desc;")[0], re.M)
+    assert names == [f[0] for f in L.mdx_merge_desc._fields_]
+
+
+def _desc(nl, nr, P=4, kt=8, base=FAKE, cap=None):
+    d = L.mdx_merge_desc()
+    d.d_left_keys, d.d_left_payload, d.n_left = base, base + (1 << 30), nl
+    d.d_right_keys, d.d_right_payload, d.n_right = base + (2 << 30), base + (3 << 30), nr
+    d.key_type, d.P = kt, P
+    d.d_out_key, d.d_out_lpay, d.d_out_rpay = base + (4 << 30), base + (5 << 30), base + (6 << 30)
+    d.out_capacity = nr if cap is None else cap
+    d.d_out_offsets, d.d_status = base + (7 << 30), None
+    return d
+
+
+def _batch_bytes(descs, lanes):
+    arr = (L.mdx_merge_desc * max(len(descs), 1))(*descs)
+    out = ctypes.c_size_t(0)
+    st = L._batch_ws(len(descs), arr, lanes, ctypes.byref(out))
+    return st, out.value
+
+
+def test_batch_workspace_plan():
+    a, b, c = _desc(100_000, 100_000, 8), _desc(60_000, 60_000, 4, 4), _desc(50_000, 50_000, 32)
+    ws = [mdx.mdx_merge_workspace_bytes(d.n_left, d.n_right, d.P, d.key_type) for d in (a, b, c)]
+    assert all(w % 256 == 0 for w in ws)
+    assert _batch_bytes([], 4) == (mdx.MDX_OK, 0)
+    assert _batch_bytes([a, b, c], 1) == (mdx.MDX_OK, max(ws))
+    # largest first, each to the lane with the fewest rows: a | b, c
+    assert _batch_bytes([c, b, a], 2) == (mdx.MDX_OK, ws[0] + max(ws[1], ws[2]))
+    assert _batch_bytes([a, b, c], 3) == (mdx.MDX_OK, sum(ws))
+    assert _batch_bytes([a, b, c], 8) == (mdx.MDX_OK, sum(ws))  # at most one lane per merge
+    for lanes in [0, mdx.MDX_MAX_LANES + 1]:
+        assert _batch_bytes([a], lanes)[0] == mdx.MDX_ERR_INVALID
+    assert _batch_bytes([_desc(10, 10, P=0)], 2)[0] == mdx.MDX_ERR_INVALID
+    out = ctypes.c_size_t(0)
+    assert L._batch_ws(-1, None, 2, ctypes.byref(out)) == mdx.MDX_ERR_INVALID
+
+
+def test_batch_validation():
+    ws = FAKE + (64 << 30)
+    good = [_desc(1000, 1000, base=FAKE + (i << 33)) for i in range(3)]
+    st, need = _batch_bytes(good, 2)
+    assert st == mdx.MDX_OK
+
+    def run(descs, lanes=2, w=ws, wb=need):
+        arr = (L.mdx_merge_desc * len(descs))(*descs)
+        return L._batch(len(descs), arr, lanes, w, wb, None)
+
+    bad = list(good); bad[1] = _desc(1000, 1000, P=0, base=FAKE + (1 << 33))
+    assert run(bad) == mdx.MDX_ERR_INVALID
+    assert "merge 1" in mdx.last_error()
+    bad = list(good); bad[2] = _desc(1000, 1000, cap=-1, base=FAKE + (2 << 33))
+    assert run(bad) == mdx.MDX_ERR_INVALID
+    assert "merge 2" in mdx.last_error()
+    assert run(good, wb=need - 256) == mdx.MDX_ERR_WORKSPACE
+    assert run(good, w=ws + 64) == mdx.MDX_ERR_INVALID      # workspace not 256-aligned
+    assert run(good, lanes=0) == mdx.MDX_ERR_INVALID
+    # an output inside the batch workspace
+    bad = list(good); bad[0] = _desc(1000, 1000, base=FAKE); bad[0].d_out_rpay = ws + 512
+    assert run(bad) == mdx.MDX_ERR_INVALID
+    assert L._batch(-1, None, 2, ws, need, None) == mdx.MDX_ERR_INVALID
+    assert L._batch(2, None, 2, ws, need, None) == mdx.MDX_ERR_INVALID

@@ -1,0 +1,121 @@
+"""Parity of mdx_merge_batch (many merges in one call) with the oracle.
+
+Every merge of a batch must equal what the oracle computes for it (rows
+after canonical ordering, per-partition offsets exact), whatever the number
+of lanes, and a batch captured into a HIP graph must give the same result
+on every replay."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from tests.gpu_util import announce, assert_join_equals_oracle, dev, host, require_gpu
+from workloads import batch_specs, batch_tables, edge_tables
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _batch_inputs():
+    """A mixed batch: log-uniform sizes (some below one tile), both key
+    widths, several P, empty sides, and one merge whose repeated key sends
+    the device to the global-table fallback."""
+    items = []
+    for s in batch_specs(36, seed=11, lo=1, hi=2e5):
+        kl, vl, kr, vr = batch_tables(s, seed=11)
+        items.append((kl, vl, kr, vr, [1, 3, 8, 32][s.index % 4]))
+    for name in ["empty_left", "empty_right", "both_empty", "int32_negative"]:
+        kl, vl, kr, vr, _ = edge_tables(name)
+        items.append((kl, vl, kr, vr, 5))
+    kl = np.full(20000, 5, np.int64)
+    kr = np.concatenate([np.full(300, 5, np.int64), np.arange(10, 5000, dtype=np.int64)])
+    items.append((kl, np.arange(kl.size, dtype=np.int64), kr, np.arange(kr.size, dtype=np.int64), 4))
+    return items
+
+
+def _jobs(items):
+    import paper_2101_08878_amd as mdx
+    jobs = []
+    for kl, vl, kr, vr, P in items:
+        cap = max(oracle.join(kl, vl, kr, vr, materialize=False)["total"], 1)
+        jobs.append(mdx.MergeJob(dev(kl), dev(vl), dev(kr), dev(vr), P, cap,
+                                 status=torch.zeros(1, dtype=torch.int32, device="cuda")))
+    return jobs
+
+
+def _check(items, jobs):
+    for i, ((kl, vl, kr, vr, P), j) in enumerate(zip(items, jobs)):
+        got = dict(key=host(j.out[0]), lpay=host(j.out[1]), rpay=host(j.out[2]),
+                   off=host(j.out_offsets), status=int(j.status.item()), cap=j.out_capacity)
+        try:
+            assert_join_equals_oracle(kl, vl, kr, vr, P, got)
+        except AssertionError as e:
+            raise AssertionError(f"merge {i} (nL={kl.size}, nR={kr.size}, P={P}): {e}") from e
+
+
+@pytest.mark.parametrize("lanes", [1, 3, 8])
+def test_batch_matches_oracle(lanes):
+    import paper_2101_08878_amd as mdx
+    announce(f"merge batch lanes={lanes}")
+    items = _batch_inputs()
+    jobs = _jobs(items)
+    mdx.mdx_merge_batch(jobs, lanes=lanes)
+    torch.cuda.synchronize()
+    _check(items, jobs)
+
+
+def test_batch_single_and_empty():
+    import paper_2101_08878_amd as mdx
+    announce("merge batch of one and of none")
+    items = _batch_inputs()[:1]
+    jobs = _jobs(items)
+    mdx.mdx_merge_batch(jobs, lanes=4)
+    torch.cuda.synchronize()
+    _check(items, jobs)
+    assert mdx.mdx_merge_batch([], lanes=4) == []
+
+
+def test_batch_graph_replays():
+    """Capture one batch (4 lanes) into a graph; replay it three times,
+    clearing the outputs with eager work in between, and check every
+    replay against the oracle."""
+    import paper_2101_08878_amd as mdx
+    announce("merge batch in a HIP graph")
+    items = _batch_inputs()
+    jobs = _jobs(items)
+    ws = torch.empty(mdx.mdx_merge_batch_workspace_bytes(jobs, 4), dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        mdx.mdx_merge_batch(jobs, lanes=4, workspace=ws, stream=s)  # lanes exist before capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        mdx.mdx_merge_batch(jobs, lanes=4, workspace=ws, stream=s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for j in jobs:
+            for t in j.out:
+                t.fill_(-1)
+            j.out_offsets.fill_(-1)
+            j.status.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        _check(items, jobs)
+
+
+def test_batch_config4_subset():
+    """The first 16 merges of the 4096-merge batch at their real sizes (up to
+    4E6 rows per side, P = 8), 4 lanes."""
+    import paper_2101_08878_amd as mdx
+    announce("merge batch: first 16 merges of the 4096-merge batch")
+    items = [(*batch_tables(s), 8) for s in batch_specs(4096)[:16]]
+    jobs = _jobs(items)
+    mdx.mdx_merge_batch(jobs, lanes=4)
+    torch.cuda.synchronize()
+    _check(items, jobs)

@@ -15,7 +15,10 @@ one int64 payload.  The generators below reproduce that shape; see
 
 from .merge_inputs import (  # noqa: F401
     CONFIGS,
+    BatchMerge,
     WorkloadSpec,
+    batch_specs,
+    batch_tables,
     config_inputs,
     match_fraction_tables,
     uniform_tables,

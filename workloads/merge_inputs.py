@@ -151,3 +151,34 @@ def config_inputs(name: str, seed: int | None = None, scale: float = 1.0):
     if spec.kind == "zipf":
         return zipf_tables(nl, nr, spec.zipf_s, spec.zipf_support, seed, kd)
     raise ValueError(spec.kind)
+
+
+@dataclass(frozen=True)
+class BatchMerge:
+    """One merge of a batch: its index, sizes and key type."""
+    index: int
+    n_left: int
+    n_right: int
+    key_dtype: str
+
+
+def batch_specs(count: int, seed: int = 0, lo: float = 1e3, hi: float = 4e6):
+    """Sizes of a batch of merges: n_left and n_right independently
+    log-uniform in [lo, hi] (rounded), key type int32 or int64 with
+    probability 1/2 each; drawn merge by merge in that order."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        nl = int(round(np.exp(rng.uniform(np.log(lo), np.log(hi)))))
+        nr = int(round(np.exp(rng.uniform(np.log(lo), np.log(hi)))))
+        kd = "int32" if rng.random() < 0.5 else "int64"
+        out.append(BatchMerge(i, nl, nr, kd))
+    return out
+
+
+def batch_tables(spec: BatchMerge, frac: float = 0.3, seed: int = 0):
+    """Tables of one batch merge: match_fraction_tables with the merge's
+    sizes and key type, seeded by (seed, index)."""
+    return match_fraction_tables(spec.n_left, spec.n_right, frac,
+                                 seed=np.random.SeedSequence([seed, spec.index]),
+                                 key_dtype=np.dtype(spec.key_dtype))
