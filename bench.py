@@ -35,10 +35,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="paper", choices=["paper", "plain", "batched"])
+    ap.add_argument("--config", default="paper", choices=["paper", "plain", "batched", "serving"])
     ap.add_argument("--batch-count", type=int, default=4096,
                     help="batched: number of merges (4096 = the full batch)")
     ap.add_argument("--lanes", type=int, default=4, help="batched: concurrent lanes")
+    ap.add_argument("--duration", type=float, default=60.0, help="serving: seconds of arrivals")
+    ap.add_argument("--rate", type=float, default=2000.0, help="serving: requests per second")
+    ap.add_argument("--slots", type=int, default=8, help="serving: concurrent slots")
+    ap.add_argument("--budget-gb", type=float, default=200.0, help="serving: HBM budget")
     ap.add_argument("--graph-merges", type=int, default=256,
                     help="batched: merges captured per HIP graph (graphs replay in order)")
     ap.add_argument("--cpu-baseline", default="on", choices=["on", "off"])
@@ -301,6 +305,117 @@ def run_batched(args):
     print(json.dumps(line), flush=True)
 
 
+def serve_run(torch, mdx, reqs, pool, slots, budget, dev, max_rows):
+    """Serve `reqs` (arrival s, nL, nR, pool index) as they arrive; returns
+    (latencies in ms, elapsed s).  A request is admitted when a slot, an
+    output buffer and the memory budget allow, in arrival order."""
+    from collections import deque
+
+    nbuf = slots + 4
+    bufs = [(torch.empty(max_rows, dtype=torch.int64, device=dev),
+             torch.empty(max_rows, dtype=torch.int64, device=dev),
+             torch.empty(max_rows, dtype=torch.int64, device=dev),
+             torch.empty(9, dtype=torch.int64, device=dev)) for _ in range(nbuf)]
+    free = list(range(nbuf))
+    status = torch.zeros(len(reqs), dtype=torch.int32, device=dev)
+    lat = [0.0] * len(reqs)
+    owner = {}
+    queue = deque()
+    nxt = done = 0
+    with mdx.Server(slots, max_rows, max_rows, 8, budget, device=dev) as srv:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while done < len(reqs):
+            now = time.perf_counter() - t0
+            while nxt < len(reqs) and reqs[nxt][0] <= now:
+                queue.append(nxt)
+                nxt += 1
+            while queue and free:
+                i = queue[0]
+                _, nl, nr, k = reqs[i]
+                b = bufs[free[-1]]
+                lk, rk = pool[k]
+                job = mdx.MergeJob(lk[:nl], pool[9][:nl], rk[:nr], pool[9][:nr], 8, nr,
+                                   out=b[:3], out_offsets=b[3], status=status[i:i + 1])
+                if srv.submit(job, i) is None:
+                    break
+                owner[i] = free.pop()
+                queue.popleft()
+            for i in srv.poll():
+                lat[i] = (time.perf_counter() - t0 - reqs[i][0]) * 1e3
+                free.append(owner.pop(i))
+                done += 1
+        elapsed = time.perf_counter() - t0
+    if int(status.max().item()) != 0:
+        raise SystemExit("serving: a merge reported a device status")
+    return lat, elapsed
+
+
+def run_serving(args):
+    """Serving line: a Poisson stream of merge requests (sizes log-uniform in
+    [1E4, 2E7] rows per side, int64 keys, match fraction uniform in
+    [0.1, 0.9], P=8), admitted as slots and the HBM budget free up, against
+    the plain path (one slot: one merge at a time, in arrival order).
+    Requests read prefixes of device-resident tables drawn beforehand (nine
+    match fractions 0.1 ... 0.9), so no request waits for input generation."""
+    import numpy as np
+    import torch
+
+    import paper_2101_08878_amd as mdx
+
+    dev = torch.device("cuda:0")
+    max_rows = 20_000_000
+    g = torch.Generator(device=dev)
+    pool = []
+    for k in range(9):
+        f = 0.1 * (k + 1)
+        g.manual_seed(7_000 + k)
+        lk = torch.randperm(max_rows, generator=g, device=dev, dtype=torch.int64)
+        m = int(round(f * max_rows))
+        hit = lk[torch.randint(0, max_rows, (m,), generator=g, device=dev, dtype=torch.int64)]
+        miss = torch.randint(max_rows, 2 * max_rows, (max_rows - m,), generator=g, device=dev,
+                             dtype=torch.int64)
+        rk = torch.cat([hit, miss])[torch.randperm(max_rows, generator=g, device=dev)].contiguous()
+        pool.append((lk, rk))
+    pool.append(torch.arange(max_rows, dtype=torch.int64, device=dev))  # payloads
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(0)
+    n = int(round(args.rate * args.duration))
+    arrivals = np.cumsum(rng.exponential(1.0 / args.rate, n))
+    reqs = []
+    for i in range(n):
+        nl = int(round(np.exp(rng.uniform(np.log(1e4), np.log(2e7)))))
+        nr = int(round(np.exp(rng.uniform(np.log(1e4), np.log(2e7)))))
+        f = rng.uniform(0.1, 0.9)
+        reqs.append((float(arrivals[i]), nl, nr, int(min(8, max(0, round(f * 10) - 1)))))
+    rows = sum(r[1] + r[2] for r in reqs)
+    budget = int(args.budget_gb * 1e9)
+    log(f"serving: {n} requests over {args.duration:g} s, offered {rows / args.duration:.4g} rows/s")
+    res = {}
+    for label, slots in [("continuous batching", args.slots), ("one merge at a time", 1)]:
+        lat, elapsed = serve_run(torch, mdx, reqs, pool, slots, budget, dev, max_rows)
+        p50, p99 = np.percentile(lat, 50), np.percentile(lat, 99)
+        res[label] = {"slots": slots, "p50_ms": round(float(p50), 3), "p99_ms": round(float(p99), 3),
+                      "max_ms": round(float(max(lat)), 3), "elapsed_s": round(elapsed, 3),
+                      "rows_per_s": round(rows / elapsed, 1)}
+        log(f"  {label} ({slots} slots): p50 {p50:.2f} ms, p99 {p99:.2f} ms, "
+            f"{rows / elapsed:.4g} rows/s over {elapsed:.2f} s")
+    cb = res["continuous batching"]
+    line = {
+        "metric": "serving p99 latency: Poisson 2000 merge requests/s, 1E4-2E7 rows per side, "
+                  "int64, match fraction U[0.1, 0.9], P=8, 200 GB HBM budget",
+        "value": cb["p99_ms"], "unit": "ms",
+        "n_gpus": 1, "steps": n, "warmup": 0, "ms_per_step": round(cb["elapsed_s"] * 1e3 / n, 4),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int64", "data": "synthetic",
+        "config": {"workload": f"serving: {n} requests at {args.rate:g}/s over {args.duration:g} s, "
+                               f"{args.slots} slots", "requests": n, "input_rows": rows,
+                   "offered_rows_per_s": round(rows / args.duration, 1)},
+        "modes": res,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -312,6 +427,9 @@ def main():
 
     if args.config == "batched":
         run_batched(args)
+        return
+    if args.config == "serving":
+        run_serving(args)
         return
 
     import torch

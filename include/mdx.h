@@ -70,6 +70,8 @@ extern "C" {
                                overlapping input/output, misaligned buffer */
 #define MDX_ERR_WORKSPACE 2 /* workspace or table smaller than its *_bytes() */
 #define MDX_ERR_HIP 3       /* a HIP runtime call or kernel launch failed */
+#define MDX_BUSY 4          /* not an error: mdx_server_submit found no free
+                               slot or memory budget; nothing was enqueued */
 
 /* Key types: the value is the key width in bytes. */
 #define MDX_KEY_I32 4
@@ -272,6 +274,56 @@ int32_t mdx_merge_batch_workspace_bytes(int32_t count, const mdx_merge_desc *h_d
 
 int32_t mdx_merge_batch(int32_t count, const mdx_merge_desc *h_descs, int32_t lanes, void *d_ws,
                         size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Serving: merge requests admitted as slots and memory free up.
+ *
+ * For a service that answers a stream of merge requests (each one a merge of
+ * Section V-B): a server owns `slots` slots, each a HIP stream (created at
+ * the default priority), a completion event and a slice of d_ws sized for
+ * the largest merge it accepts (n_left <= max_left, n_right <= max_right,
+ * P <= max_P, either key type).  mdx_server_submit admits a merge into a
+ * free slot if the bytes of the merges in flight plus this one's -- inputs
+ * and outputs: (n_left + n_right)(key bytes + 8) + out_capacity (key bytes
+ * + 16) + 8 (P + 1) -- stay within budget_bytes; otherwise it returns
+ * MDX_BUSY and enqueues nothing.  Merges in different slots run
+ * concurrently and overlap on the device; each computes exactly what
+ * mdx_merge computes with the same arguments.  mdx_server_poll returns the
+ * tags of merges that have finished (their outputs are complete and
+ * visible to any stream) and frees their slots and budget.  `ready`, if not
+ * NULL, is an event the merge waits for before reading its inputs.
+ *
+ * A server is used from one host thread at a time.  The caller keeps d_ws
+ * and every submitted merge's buffers alive until the merge is polled or
+ * the server destroyed; mdx_server_destroy waits for merges in flight and
+ * releases the streams and events.  Errors: MDX_ERR_INVALID for slots
+ * outside [1, MDX_MAX_SLOTS], bad limits, a descriptor mdx_merge would
+ * reject, a merge beyond the limits or larger than the whole budget;
+ * MDX_ERR_WORKSPACE for a short workspace; MDX_ERR_HIP for runtime
+ * failures.
+ * ------------------------------------------------------------------------- */
+#define MDX_MAX_SLOTS 32
+
+typedef struct mdx_server mdx_server;
+
+int32_t mdx_server_workspace_bytes(int32_t slots, int64_t max_left, int64_t max_right,
+                                   int32_t max_P, size_t *h_bytes);
+
+int32_t mdx_server_create(int32_t slots, int64_t max_left, int64_t max_right, int32_t max_P,
+                          size_t budget_bytes, void *d_ws, size_t ws_bytes,
+                          mdx_server **h_server);
+
+int32_t mdx_server_submit(mdx_server *server, const mdx_merge_desc *h_desc, int64_t tag,
+                          hipEvent_t ready, int32_t *h_slot);
+
+int32_t mdx_server_poll(mdx_server *server, int64_t *h_tags, int32_t capacity,
+                        int32_t *h_count);
+
+/* Busy slots and bytes in flight (host-side bookkeeping; no device call). */
+int32_t mdx_server_stats(const mdx_server *server, int32_t *h_busy_slots,
+                         size_t *h_bytes_in_flight);
+
+int32_t mdx_server_destroy(mdx_server *server);
 
 /* ---------------------------------------------------------------------------
  * Kernel timing for benchmarks.

@@ -30,6 +30,7 @@ MDX_OK = 0
 MDX_ERR_INVALID = 1
 MDX_ERR_WORKSPACE = 2
 MDX_ERR_HIP = 3
+MDX_BUSY = 4
 MDX_KEY_I32 = 4
 MDX_KEY_I64 = 8
 MDX_DEV_OUTPUT_OVERFLOW = 1
@@ -37,6 +38,7 @@ MDX_DEV_BAD_PARTITIONING = 2
 MDX_DEV_SCAN_TIMEOUT = 4
 MDX_MAX_P = 4096
 MDX_MAX_LANES = 8
+MDX_MAX_SLOTS = 32
 
 _i32, _i64, _sz, _vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p
 
@@ -86,6 +88,15 @@ _batch_ws = _sig("mdx_merge_batch_workspace_bytes", _i32, _i32, ctypes.POINTER(m
                  ctypes.POINTER(_sz))
 _batch = _sig("mdx_merge_batch", _i32, _i32, ctypes.POINTER(mdx_merge_desc), _i32, _vp, _sz, _vp)
 
+_srv_ws = _sig("mdx_server_workspace_bytes", _i32, _i32, _i64, _i64, _i32, ctypes.POINTER(_sz))
+_srv_create = _sig("mdx_server_create", _i32, _i32, _i64, _i64, _i32, _sz, _vp, _sz,
+                   ctypes.POINTER(_vp))
+_srv_submit = _sig("mdx_server_submit", _i32, _vp, ctypes.POINTER(mdx_merge_desc), _i64, _vp,
+                   ctypes.POINTER(_i32))
+_srv_poll = _sig("mdx_server_poll", _i32, _vp, ctypes.POINTER(_i64), _i32, ctypes.POINTER(_i32))
+_srv_stats = _sig("mdx_server_stats", _i32, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_sz))
+_srv_destroy = _sig("mdx_server_destroy", _i32, _vp)
+
 _trace = _sig("mdx_trace_kernel", _i32, ctypes.c_char_p, _vp, _vp, _i32, ctypes.POINTER(_i32))
 
 ABI_FUNCTIONS = [
@@ -95,6 +106,8 @@ ABI_FUNCTIONS = [
     "mdx_join_probe_workspace_bytes", "mdx_join_probe",
     "mdx_merge_workspace_bytes", "mdx_merge",
     "mdx_merge_batch_workspace_bytes", "mdx_merge_batch",
+    "mdx_server_workspace_bytes", "mdx_server_create", "mdx_server_submit", "mdx_server_poll",
+    "mdx_server_stats", "mdx_server_destroy",
     "mdx_trace_kernel",
 ]
 TRACEABLE_KERNELS = ["part_hist", "part_scatter", "seg_scatter", "rj_join", "tbl_init",
@@ -373,6 +386,81 @@ def mdx_merge_batch(jobs, *, lanes: int = 4, workspace=None, stream=None):
     _check(_batch(len(jobs), descs, int(lanes), _dev(workspace, "workspace"),
                   workspace.numel() * workspace.element_size(), _stream(stream)))
     return jobs
+
+
+# ---- serving ------------------------------------------------------------------------------
+
+def mdx_server_workspace_bytes(slots: int, max_left: int, max_right: int, max_P: int) -> int:
+    return _bytes(_srv_ws, int(slots), int(max_left), int(max_right), int(max_P))
+
+
+class Server:
+    """Merge requests admitted as slots and memory free up (mdx_server_*).
+
+    submit() returns the slot a MergeJob went to, or None when no slot or
+    budget is free (nothing enqueued); poll() returns the tags of finished
+    merges.  The server keeps each job (and so its buffers) until it is
+    polled.  One host thread at a time."""
+
+    def __init__(self, slots: int, max_left: int, max_right: int, max_P: int,
+                 budget_bytes: int, device=None):
+        device = torch.device("cuda") if device is None else device
+        need = mdx_server_workspace_bytes(slots, max_left, max_right, max_P)
+        self.workspace = _workspace(need, device)
+        h = _vp()
+        _check(_srv_create(int(slots), int(max_left), int(max_right), int(max_P), int(budget_bytes),
+                           _dev(self.workspace, "workspace"), self.workspace.numel(), ctypes.byref(h)))
+        self._h = h
+        self._tags = (_i64 * int(slots))()
+        self._jobs = {}
+
+    def submit(self, job: MergeJob, tag: int, ready=None):
+        if self._h is None:
+            raise MdxError(MDX_ERR_INVALID, "server is closed")
+        dev = job.left_keys.device
+        if job.out is None:
+            job.out = _outputs(job.out_capacity, job.left_keys.dtype, dev, None)
+        if job.out_offsets is None:
+            job.out_offsets = torch.empty(job.P + 1, dtype=torch.int64, device=dev)
+        desc = _batch_descs([job], True)
+        slot = _i32(-1)
+        st = _srv_submit(self._h, desc, int(tag), ready, ctypes.byref(slot))
+        if st == MDX_BUSY:
+            return None
+        _check(st)
+        self._jobs[int(tag)] = job
+        return slot.value
+
+    def poll(self):
+        n = _i32(0)
+        _check(_srv_poll(self._h, self._tags, len(self._tags), ctypes.byref(n)))
+        done = [self._tags[i] for i in range(n.value)]
+        for t in done:
+            self._jobs.pop(t, None)
+        return done
+
+    def stats(self):
+        b, nbytes = _i32(0), _sz(0)
+        _check(_srv_stats(self._h, ctypes.byref(b), ctypes.byref(nbytes)))
+        return b.value, nbytes.value
+
+    def close(self):
+        if self._h is not None:
+            h, self._h = self._h, None
+            _check(_srv_destroy(h))
+            self._jobs.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---- kernel tracing (benchmarks) -------------------------------------------------------

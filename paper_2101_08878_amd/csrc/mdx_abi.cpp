@@ -143,6 +143,8 @@ const char *mdx_status_string(int32_t status)
         return "workspace or table too small";
     case MDX_ERR_HIP:
         return "HIP runtime error";
+    case MDX_BUSY:
+        return "busy: no free slot or memory budget (nothing enqueued)";
     default:
         return "unknown status";
     }
@@ -830,6 +832,225 @@ int32_t mdx_merge_batch(int32_t count, const mdx_merge_desc *h_descs, int32_t la
             (void)hipEventDestroy(fork);
     }
     return e == hipSuccess ? MDX_OK : hip_fail(e, W);
+}
+
+// ---- serving: merges admitted as slots and memory free up ------------------------------
+
+}  // extern "C"
+
+struct mdx_server {
+    int device = 0;
+    int32_t slots = 0;
+    int64_t max_left = 0, max_right = 0;
+    int32_t max_P = 0;
+    size_t budget = 0, in_flight = 0, slot_bytes = 0;
+    char *d_ws = nullptr;
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> done;
+    std::vector<int64_t> tag;       // tag of the merge in the slot
+    std::vector<size_t> held;       // its bytes against the budget
+    std::vector<char> busy;
+};
+
+namespace {
+
+// Workspace of one slot: the largest merge layout over both key types and
+// every P up to max_P at the largest sizes.
+size_t server_slot_bytes(int64_t max_left, int64_t max_right, int32_t max_P)
+{
+    size_t b = 0;
+    for (int32_t P = 1; P <= max_P; ++P)
+        for (int32_t kt : {MDX_KEY_I32, MDX_KEY_I64}) {
+            const size_t x = merge_layout(max_left, max_right, P, kt).bytes;
+            b = x > b ? x : b;
+        }
+    return align_up(b);
+}
+
+// Bytes a merge holds while it runs: its inputs and outputs.
+size_t request_bytes(const mdx_merge_desc &d)
+{
+    const size_t row = (size_t)d.key_type + 8;
+    return (size_t)d.n_left * row + (size_t)d.n_right * row +
+           (size_t)d.out_capacity * ((size_t)d.key_type + 16) + (size_t)(d.P + 1) * 8;
+}
+
+int32_t check_server_limits(int32_t slots, int64_t max_left, int64_t max_right, int32_t max_P,
+                            const char *W)
+{
+    if (slots < 1 || slots > MDX_MAX_SLOTS)
+        return fail(MDX_ERR_INVALID, std::string(W) + ": slots outside [1, MDX_MAX_SLOTS]");
+    if (int32_t e = check_sizes(max_left, max_P, MDX_KEY_I64, W))
+        return e;
+    return check_sizes(max_right, max_P, MDX_KEY_I64, W);
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t mdx_server_workspace_bytes(int32_t slots, int64_t max_left, int64_t max_right,
+                                   int32_t max_P, size_t *h_bytes)
+{
+    g_err.clear();
+    const char *W = "mdx_server_workspace_bytes";
+    if (int32_t e = check_server_limits(slots, max_left, max_right, max_P, W))
+        return e;
+    if (!h_bytes)
+        return fail(MDX_ERR_INVALID, std::string(W) + ": h_bytes is null");
+    *h_bytes = (size_t)slots * server_slot_bytes(max_left, max_right, max_P);
+    return MDX_OK;
+}
+
+int32_t mdx_server_create(int32_t slots, int64_t max_left, int64_t max_right, int32_t max_P,
+                          size_t budget_bytes, void *d_ws, size_t ws_bytes,
+                          mdx_server **h_server)
+{
+    g_err.clear();
+    const char *W = "mdx_server_create";
+    if (int32_t e = check_server_limits(slots, max_left, max_right, max_P, W))
+        return e;
+    if (!h_server)
+        return fail(MDX_ERR_INVALID, std::string(W) + ": h_server is null");
+    *h_server = nullptr;
+    const size_t per = server_slot_bytes(max_left, max_right, max_P);
+    if (!d_ws || !aligned(d_ws, kAlign))
+        return fail(MDX_ERR_INVALID, std::string(W) + ": workspace null or not 256-byte aligned");
+    if (ws_bytes < (size_t)slots * per)
+        return fail(MDX_ERR_WORKSPACE, std::string(W) + ": workspace needs " +
+                                           std::to_string((size_t)slots * per) + " bytes");
+    auto *srv = new mdx_server;
+    srv->slots = slots;
+    srv->max_left = max_left;
+    srv->max_right = max_right;
+    srv->max_P = max_P;
+    srv->budget = budget_bytes;
+    srv->slot_bytes = per;
+    srv->d_ws = (char *)d_ws;
+    srv->tag.assign((size_t)slots, -1);
+    srv->held.assign((size_t)slots, 0);
+    srv->busy.assign((size_t)slots, 0);
+    hipError_t e = hipGetDevice(&srv->device);
+    for (int32_t i = 0; i < slots && e == hipSuccess; ++i) {
+        hipStream_t st;
+        e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e != hipSuccess)
+            break;
+        srv->streams.push_back(st);
+        hipEvent_t ev;
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess)
+            break;
+        srv->done.push_back(ev);
+    }
+    if (e != hipSuccess) {
+        mdx_server_destroy(srv);
+        return hip_fail(e, W);
+    }
+    *h_server = srv;
+    return MDX_OK;
+}
+
+int32_t mdx_server_submit(mdx_server *srv, const mdx_merge_desc *h_desc, int64_t tag,
+                          hipEvent_t ready, int32_t *h_slot)
+{
+    g_err.clear();
+    const char *W = "mdx_server_submit";
+    if (!srv || !h_desc || !h_slot)
+        return fail(MDX_ERR_INVALID, std::string(W) + ": null server, descriptor or h_slot");
+    const mdx_merge_desc &d = *h_desc;
+    if (int32_t e = check_merge(d, W))
+        return e;
+    if (d.n_left > srv->max_left || d.n_right > srv->max_right || d.P > srv->max_P)
+        return fail(MDX_ERR_INVALID, std::string(W) + ": merge larger than the server's limits");
+    const size_t need = request_bytes(d);
+    if (need > srv->budget)
+        return fail(MDX_ERR_INVALID, std::string(W) + ": merge alone exceeds the memory budget");
+    *h_slot = -1;
+    int32_t s = -1;
+    for (int32_t i = 0; i < srv->slots; ++i)
+        if (!srv->busy[(size_t)i]) {
+            s = i;
+            break;
+        }
+    if (s < 0 || srv->in_flight + need > srv->budget)
+        return MDX_BUSY;
+    char *ws = srv->d_ws + (size_t)s * srv->slot_bytes;
+    if (int32_t e = check_merge_ws(d, ws, srv->slot_bytes,
+                                   merge_layout(d.n_left, d.n_right, d.P, d.key_type).bytes, W))
+        return e;
+    if (int32_t e = check_merge_ws(d, srv->d_ws, (size_t)srv->slots * srv->slot_bytes, 0, W))
+        return e;
+    hipStream_t st = srv->streams[(size_t)s];
+    hipError_t e = ready ? hipStreamWaitEvent(st, ready, 0) : hipSuccess;
+    if (e == hipSuccess)
+        e = enqueue_merge(d, ws, st);
+    if (e == hipSuccess)
+        e = hipEventRecord(srv->done[(size_t)s], st);
+    if (e != hipSuccess)
+        return hip_fail(e, W);
+    srv->busy[(size_t)s] = 1;
+    srv->tag[(size_t)s] = tag;
+    srv->held[(size_t)s] = need;
+    srv->in_flight += need;
+    *h_slot = s;
+    return MDX_OK;
+}
+
+int32_t mdx_server_poll(mdx_server *srv, int64_t *h_tags, int32_t capacity, int32_t *h_count)
+{
+    g_err.clear();
+    const char *W = "mdx_server_poll";
+    if (!srv || !h_count || capacity < 0 || (capacity > 0 && !h_tags))
+        return fail(MDX_ERR_INVALID, std::string(W) + ": bad arguments");
+    int32_t n = 0;
+    for (int32_t i = 0; i < srv->slots && n < capacity; ++i) {
+        if (!srv->busy[(size_t)i])
+            continue;
+        const hipError_t e = hipEventQuery(srv->done[(size_t)i]);
+        if (e == hipErrorNotReady)
+            continue;
+        if (e != hipSuccess)
+            return hip_fail(e, W);
+        h_tags[n++] = srv->tag[(size_t)i];
+        srv->busy[(size_t)i] = 0;
+        srv->tag[(size_t)i] = -1;
+        srv->in_flight -= srv->held[(size_t)i];
+        srv->held[(size_t)i] = 0;
+    }
+    *h_count = n;
+    return MDX_OK;
+}
+
+int32_t mdx_server_stats(const mdx_server *srv, int32_t *h_busy_slots, size_t *h_bytes_in_flight)
+{
+    g_err.clear();
+    if (!srv || !h_busy_slots || !h_bytes_in_flight)
+        return fail(MDX_ERR_INVALID, "mdx_server_stats: null argument");
+    int32_t b = 0;
+    for (char x : srv->busy)
+        b += x ? 1 : 0;
+    *h_busy_slots = b;
+    *h_bytes_in_flight = srv->in_flight;
+    return MDX_OK;
+}
+
+int32_t mdx_server_destroy(mdx_server *srv)
+{
+    g_err.clear();
+    if (!srv)
+        return MDX_OK;
+    hipError_t first = hipSuccess;
+    for (hipStream_t st : srv->streams) {
+        const hipError_t e = hipStreamSynchronize(st);  // merges in flight finish first
+        if (first == hipSuccess)
+            first = e;
+        (void)hipStreamDestroy(st);
+    }
+    for (hipEvent_t ev : srv->done)
+        (void)hipEventDestroy(ev);
+    delete srv;
+    return first == hipSuccess ? MDX_OK : hip_fail(first, "mdx_server_destroy");
 }
 
 }  // extern "C"

@@ -39,7 +39,7 @@ def test_constants_match_header():
     h = _header()
     for name in ["MDX_OK", "MDX_ERR_INVALID", "MDX_ERR_WORKSPACE", "MDX_ERR_HIP", "MDX_KEY_I32",
                  "MDX_KEY_I64", "MDX_DEV_OUTPUT_OVERFLOW", "MDX_DEV_BAD_PARTITIONING",
-                 "MDX_DEV_SCAN_TIMEOUT", "MDX_MAX_P",
+                 "MDX_DEV_SCAN_TIMEOUT", "MDX_MAX_P", "MDX_BUSY", "MDX_MAX_LANES", "MDX_MAX_SLOTS",
                  "MDX_ABI_VERSION"]:
         m = re.search(rf"#define\s+{name}\s+(\d+)", h)
         assert m, name
@@ -199,3 +199,27 @@ def test_batch_validation():
     assert run(bad) == mdx.MDX_ERR_INVALID
     assert L._batch(-1, None, 2, ws, need, None) == mdx.MDX_ERR_INVALID
     assert L._batch(2, None, 2, ws, need, None) == mdx.MDX_ERR_INVALID
+
+
+def test_server_workspace_and_validation():
+    """Server sizing and every argument check that runs before a stream or
+    event is created (no GPU needed)."""
+    per = max(mdx.mdx_merge_workspace_bytes(10**6, 2 * 10**6, P, kt)
+              for P in range(1, 9) for kt in (4, 8))
+    assert mdx.mdx_server_workspace_bytes(3, 10**6, 2 * 10**6, 8) == 3 * per
+    out = ctypes.c_size_t(0)
+    for args in [(0, 10, 10, 8), (mdx.MDX_MAX_SLOTS + 1, 10, 10, 8), (2, -1, 10, 8), (2, 10, 10, 0)]:
+        assert L._srv_ws(*args, ctypes.byref(out)) == mdx.MDX_ERR_INVALID
+    h = ctypes.c_void_p()
+    need = mdx.mdx_server_workspace_bytes(2, 1000, 1000, 4)
+    assert L._srv_create(0, 1000, 1000, 4, 1 << 30, FAKE, need, ctypes.byref(h)) == mdx.MDX_ERR_INVALID
+    assert L._srv_create(2, 1000, 1000, 4, 1 << 30, FAKE, need - 256, ctypes.byref(h)) == mdx.MDX_ERR_WORKSPACE
+    assert L._srv_create(2, 1000, 1000, 4, 1 << 30, FAKE + 64, need, ctypes.byref(h)) == mdx.MDX_ERR_INVALID
+    assert L._srv_create(2, 1000, 1000, 4, 1 << 30, None, need, ctypes.byref(h)) == mdx.MDX_ERR_INVALID
+    assert L._srv_create(2, 1000, 1000, 4, 1 << 30, FAKE, need, None) == mdx.MDX_ERR_INVALID
+    slot, n = ctypes.c_int32(0), ctypes.c_int32(0)
+    d = _desc(100, 100)
+    assert L._srv_submit(None, ctypes.byref(d), 1, None, ctypes.byref(slot)) == mdx.MDX_ERR_INVALID
+    assert L._srv_poll(None, None, 0, ctypes.byref(n)) == mdx.MDX_ERR_INVALID
+    assert L._srv_destroy(None) == mdx.MDX_OK
+    assert "busy" in mdx.status_string(mdx.MDX_BUSY)
