@@ -123,3 +123,20 @@ def match_counts(lkeys, rkeys) -> np.ndarray:
     if rc != 0:
         raise ValueError("oracle_match_counts failed")
     return out
+
+
+def transpose_sum(x) -> np.ndarray:
+    """y = x + x^T for a square float64 matrix.
+
+    arXiv 2101.08878, Section V-B ("Sum of cuPy Array and its Transpose"):
+    the benchmark evaluates y = x + x.T on a chunked cuPy array (16K x 16K,
+    4K chunks on RI2).  The plain definition: every element y[i, j] is the
+    IEEE-754 double sum (round to nearest, ties to even) of x[i, j] and
+    x[j, i]; numpy's elementwise add of x and its transposed view computes
+    exactly that.  The paper does not state the element type; cuPy's random
+    arrays are float64, which is the reading taken here.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    if x.ndim != 2 or x.shape[0] != x.shape[1]:
+        raise ValueError("transpose_sum needs a square matrix")
+    return x + x.T

@@ -323,3 +323,45 @@ def test_match_counts_brute_force():
     want = np.array([int(np.sum(kl == k)) for k in kr], np.int64)
     assert np.array_equal(got, want)
     assert got.sum() == oracle.join(kl, vl, kr, vr, materialize=False)["total"]
+
+
+# ---- transpose sum (the cuPy benchmark's y = x + x.T) -------------------------------
+
+def _read_example(golden_dir):
+    rows = [ln.split() for ln in open(os.path.join(golden_dir, "transpose_sum_example.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    vals = np.array(rows, dtype=np.float64)
+    return vals[:3], vals[3:]
+
+
+def test_transpose_sum_worked_example(golden_dir):
+    x, y = _read_example(golden_dir)
+    assert np.array_equal(oracle.transpose_sum(x), y)
+
+
+def test_transpose_sum_invariants():
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((97, 97)) * 10.0 ** rng.integers(-30, 30, (97, 97))
+    y = oracle.transpose_sum(x)
+    # IEEE addition commutes: the result is symmetric bit for bit
+    assert np.array_equal(y.view(np.uint64), y.T.view(np.uint64))
+    # the diagonal is doubled exactly (x + x = 2x, no rounding)
+    assert np.array_equal(np.diag(y), 2.0 * np.diag(x))
+    # x + x^T - x^T recovers x only up to rounding: not the identity map
+    assert not np.array_equal(y, x)
+
+
+def test_transpose_sum_rounding_pin():
+    """1 + 2^-53 lies halfway between 1 and the next double: ties to even
+    gives 1.0; 1 + 3 2^-53 rounds up to 1 + 2^-51."""
+    x = np.array([[0.0, 1.0, 1.0], [2.0 ** -53, 0.0, 0.0], [3 * 2.0 ** -53, 0.0, 0.0]])
+    y = oracle.transpose_sum(x)
+    assert y[0, 1] == 1.0 and y[1, 0] == 1.0
+    assert y[0, 2] == 1.0 + 2.0 ** -51
+
+
+def test_transpose_sum_edge_shapes():
+    assert oracle.transpose_sum(np.zeros((0, 0))).shape == (0, 0)
+    assert oracle.transpose_sum(np.array([[2.5]]))[0, 0] == 5.0
+    with pytest.raises(ValueError):
+        oracle.transpose_sum(np.zeros((2, 3)))
