@@ -35,7 +35,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="paper", choices=["paper", "plain", "batched", "serving"])
+    ap.add_argument("--config", default="paper", choices=["paper", "plain", "batched", "serving", "transpose"])
     ap.add_argument("--batch-count", type=int, default=4096,
                     help="batched: number of merges (4096 = the full batch)")
     ap.add_argument("--lanes", type=int, default=4, help="batched: concurrent lanes")
@@ -416,6 +416,71 @@ def run_serving(args):
     print(json.dumps(line), flush=True)
 
 
+def run_transpose(args):
+    """The paper's other local workload (Section V-B, cuPy benchmark): y =
+    x + x^T on the RI2 array, 16384 x 16384 float64.  Algorithmic bytes:
+    each element read once and written once (16 B)."""
+    import torch
+
+    import paper_2101_08878_amd as mdx
+
+    n = 16384
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(0)
+    x = torch.rand((n, n), generator=g, dtype=torch.float64, device=dev)
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        mdx.mdx_transpose_sum(x, out=y, stream=stream)
+    torch.cuda.synchronize()
+    if not torch.equal(y, x + x.T):
+        raise SystemExit("transpose sum: result differs from x + x.T")
+    tr = mdx.KernelTrace("transpose_sum", args.steps)
+    tr.start()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        mdx.mdx_transpose_sum(x, out=y, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    mdx.KernelTrace.stop_all()
+    ms = e0.elapsed_time(e1) / args.steps
+    d = tr.durations_ms()
+    tr.close()
+    kms = sum(d) / len(d)
+    nbytes = 16 * n * n
+    achieved = nbytes / (kms / 1e3) / 1e9
+    log(f"transpose sum {n} x {n}: {ms:.3f} ms/step, kernel {kms:.3f} ms, {achieved:.0f} GB/s")
+    line = {
+        "metric": "matrix elements/s for y = x + x^T, 16384 x 16384 float64",
+        "value": round(n * n / (ms / 1e3), 1), "unit": "elements/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"transpose sum: {n} x {n} float64 (the RI2 cuPy array)", "n": n},
+        "roofline": {"bound": "hbm", "kernel": "transpose_sum", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "bytes_per_launch": nbytes, "avg_launch_us": round(kms * 1e3, 2)},
+    }
+    if args.cpu_baseline == "on":
+        import numpy as np
+
+        import oracle
+        m = 8192
+        xs = np.random.default_rng(0).random((m, m))
+        t0 = time.perf_counter()
+        reps = 0
+        while time.perf_counter() - t0 < 10.0:
+            oracle.transpose_sum(xs)
+            reps += 1
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": reps * m * m / dt, "unit": "elements/s", "cores": 1,
+                                "kind": "oracle",
+                                "sample": f"{reps} x numpy x + x.T on {m} x {m} float64, {dt:.2f} s"}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -430,6 +495,9 @@ def main():
         return
     if args.config == "serving":
         run_serving(args)
+        return
+    if args.config == "transpose":
+        run_transpose(args)
         return
 
     import torch

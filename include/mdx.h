@@ -326,6 +326,22 @@ int32_t mdx_server_stats(const mdx_server *server, int32_t *h_busy_slots,
 int32_t mdx_server_destroy(mdx_server *server);
 
 /* ---------------------------------------------------------------------------
+ * Sum of a matrix and its transpose (the paper's other benchmark, Section
+ * V-B "Sum of cuPy Array and its Transpose": y = x + x.T on a chunked cuPy
+ * array).
+ *
+ * y = x + x^T for an n x n row-major float64 matrix: y[i][j] is the IEEE-754
+ * sum (round to nearest, ties to even) of x[i][j] and x[j][i], so the
+ * result is the same bit for bit on any device.  d_y may equal d_x (in
+ * place); otherwise the two must not overlap.  n = 0 is valid and enqueues
+ * nothing.  Errors: MDX_ERR_INVALID for n outside [0, MDX_MAX_TRANSPOSE_N],
+ * a null or misaligned matrix with n > 0, or a partial overlap.
+ * ------------------------------------------------------------------------- */
+#define MDX_MAX_TRANSPOSE_N (INT64_C(1) << 17) /* 137 GB; the grid of tile pairs fits a dispatch */
+
+int32_t mdx_transpose_sum(const double *d_x, double *d_y, int64_t n, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Kernel timing for benchmarks.
  *
  * Brackets every launch of the named kernel, made by libmdx calls on the
@@ -337,7 +353,7 @@ int32_t mdx_server_destroy(mdx_server *server);
  * alive while tracing.  Up to 8 kernels can be traced at once; kernel ==
  * NULL stops all tracing on the thread.  Names: "part_hist", "part_scatter",
  * "seg_scatter", "rj_join", "tbl_init", "tbl_insert", "probe_chain",
- * "probe_expand".
+ * "probe_expand", "transpose_sum".
  * ------------------------------------------------------------------------- */
 int32_t mdx_trace_kernel(const char *kernel, hipEvent_t *h_starts, hipEvent_t *h_stops,
                          int32_t capacity, int32_t *h_count);

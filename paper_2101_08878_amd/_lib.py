@@ -39,6 +39,7 @@ MDX_DEV_SCAN_TIMEOUT = 4
 MDX_MAX_P = 4096
 MDX_MAX_LANES = 8
 MDX_MAX_SLOTS = 32
+MDX_MAX_TRANSPOSE_N = 1 << 17
 
 _i32, _i64, _sz, _vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p
 
@@ -97,6 +98,8 @@ _srv_poll = _sig("mdx_server_poll", _i32, _vp, ctypes.POINTER(_i64), _i32, ctype
 _srv_stats = _sig("mdx_server_stats", _i32, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_sz))
 _srv_destroy = _sig("mdx_server_destroy", _i32, _vp)
 
+_tsum = _sig("mdx_transpose_sum", _i32, _vp, _vp, _i64, _vp)
+
 _trace = _sig("mdx_trace_kernel", _i32, ctypes.c_char_p, _vp, _vp, _i32, ctypes.POINTER(_i32))
 
 ABI_FUNCTIONS = [
@@ -108,10 +111,11 @@ ABI_FUNCTIONS = [
     "mdx_merge_batch_workspace_bytes", "mdx_merge_batch",
     "mdx_server_workspace_bytes", "mdx_server_create", "mdx_server_submit", "mdx_server_poll",
     "mdx_server_stats", "mdx_server_destroy",
+    "mdx_transpose_sum",
     "mdx_trace_kernel",
 ]
 TRACEABLE_KERNELS = ["part_hist", "part_scatter", "seg_scatter", "rj_join", "tbl_init",
-                     "tbl_insert", "probe_chain", "probe_expand"]
+                     "tbl_insert", "probe_chain", "probe_expand", "transpose_sum"]
 
 
 class MdxError(RuntimeError):
@@ -461,6 +465,20 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+# ---- transpose sum ----------------------------------------------------------------------
+
+def mdx_transpose_sum(x: torch.Tensor, *, out=None, stream=None) -> torch.Tensor:
+    """y = x + x^T for a square float64 matrix (out may be x).  Asynchronous."""
+    if x.dim() != 2 or x.shape[0] != x.shape[1]:
+        raise ValueError("x must be a square matrix")
+    n = x.shape[0]
+    out = torch.empty_like(x) if out is None else out
+    if out.shape != x.shape:
+        raise ValueError("out must have the shape of x")
+    _check(_tsum(_dev(x, "x", torch.float64), _dev(out, "out", torch.float64), n, _stream(stream)))
+    return out
 
 
 # ---- kernel tracing (benchmarks) -------------------------------------------------------

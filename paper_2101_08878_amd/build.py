@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmdx.so")
-SOURCES = ["mdx_abi.cpp", "partition.hip", "join.hip", "rjoin.hip"]
+SOURCES = ["mdx_abi.cpp", "partition.hip", "join.hip", "rjoin.hip", "transpose.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -167,7 +167,7 @@ int32_t mdx_trace_kernel(const char *kernel, hipEvent_t *h_starts, hipEvent_t *h
     }
     static const char *known[] = {"part_hist", "part_scatter", "tbl_init",
                                   "tbl_insert", "probe_chain", "probe_expand",
-                                  "seg_scatter", "rj_join"};
+                                  "seg_scatter", "rj_join", "transpose_sum"};
     bool ok = false;
     for (const char *k : known)
         ok |= std::string(k) == kernel;
@@ -1051,6 +1051,25 @@ int32_t mdx_server_destroy(mdx_server *srv)
         (void)hipEventDestroy(ev);
     delete srv;
     return first == hipSuccess ? MDX_OK : hip_fail(first, "mdx_server_destroy");
+}
+
+// ---- transpose sum ----------------------------------------------------------------
+
+int32_t mdx_transpose_sum(const double *d_x, double *d_y, int64_t n, hipStream_t stream)
+{
+    g_err.clear();
+    const char *W = "mdx_transpose_sum";
+    if (n < 0 || n > MDX_MAX_TRANSPOSE_N)
+        return fail(MDX_ERR_INVALID, std::string(W) + ": n outside [0, MDX_MAX_TRANSPOSE_N]");
+    if (n == 0)
+        return MDX_OK;
+    if (!d_x || !d_y || !aligned(d_x, 8) || !aligned(d_y, 8))
+        return fail(MDX_ERR_INVALID, std::string(W) + ": null or misaligned matrix");
+    const size_t bytes = (size_t)n * (size_t)n * 8;
+    if ((const void *)d_x != (const void *)d_y && overlap(d_x, bytes, d_y, bytes))
+        return fail(MDX_ERR_INVALID, std::string(W) + ": x and y overlap without being equal");
+    const hipError_t e = launch_transpose_sum(d_x, d_y, n, stream);
+    return e == hipSuccess ? MDX_OK : hip_fail(e, W);
 }
 
 }  // extern "C"

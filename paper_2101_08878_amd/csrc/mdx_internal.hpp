@@ -345,4 +345,7 @@ hipError_t launch_rjoin_finalize(int32_t P, int qbits, const RJoinWs &w, const P
 hipError_t launch_gather_offsets(const int64_t *a, int32_t P, int stride, int64_t *out,
                                  hipStream_t s);
 
+// ---- transpose sum (y = x + x^T, float64) -------------------------------------------
+hipError_t launch_transpose_sum(const double *x, double *y, int64_t n, hipStream_t s);
+
 }  // namespace mdx

@@ -223,3 +223,16 @@ def test_server_workspace_and_validation():
     assert L._srv_poll(None, None, 0, ctypes.byref(n)) == mdx.MDX_ERR_INVALID
     assert L._srv_destroy(None) == mdx.MDX_OK
     assert "busy" in mdx.status_string(mdx.MDX_BUSY)
+
+
+def test_transpose_sum_validation():
+    E = mdx.MDX_ERR_INVALID
+    n = 100
+    assert L._tsum(FAKE, FAKE + (1 << 30), -1, None) == E
+    assert L._tsum(FAKE, FAKE + (1 << 30), (1 << 17) + 1, None) == E
+    assert L._tsum(None, FAKE, n, None) == E
+    assert L._tsum(FAKE + 4, FAKE + (1 << 30), n, None) == E       # misaligned
+    assert L._tsum(FAKE, FAKE + 8 * n, n, None) == E                # partial overlap
+    assert L._tsum(None, None, 0, None) == mdx.MDX_OK               # n = 0: nothing to do
+    m = re.search(r"#define\s+MDX_MAX_TRANSPOSE_N\s+\(INT64_C\(1\)\s*<<\s*(\d+)\)", _header())
+    assert m and L.MDX_MAX_TRANSPOSE_N == 1 << int(m.group(1))
