@@ -350,7 +350,7 @@ int32_t mdx_transpose_sum(const double *d_x, double *d_y, int64_t n, hipStream_t
  * launched on, for i = *h_count; then increments *h_count.  Launches past
  * `capacity` are not bracketed (*h_count still counts them).  The caller
  * creates and destroys the events and keeps the arrays and the counter
- * alive while tracing.  Up to 8 kernels can be traced at once; kernel ==
+ * alive while tracing.  Up to 16 kernels can be traced at once; kernel ==
  * NULL stops all tracing on the thread.  Names: "part_hist", "part_scatter",
  * "seg_scatter", "rj_join", "tbl_init", "tbl_insert", "probe_chain",
  * "probe_expand", "transpose_sum".

@@ -75,7 +75,7 @@ struct Trace {
     int32_t cap = 0;
     int32_t *count = nullptr;
 };
-constexpr int kMaxTraces = 8;
+constexpr int kMaxTraces = 16;
 thread_local Trace g_trace[kMaxTraces];
 thread_local int g_ntrace = 0;
 
