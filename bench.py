@@ -424,8 +424,12 @@ def run_transpose(args):
 
     import paper_2101_08878_amd as mdx
 
+    from paper_2101_08878_amd.rocprof_summary import kernel_sources_hash
+
     n = 16384
     dev = torch.device("cuda:0")
+    copy = copy_ceiling(torch, dev)
+    log(f"plain copy of {copy['bytes'] >> 20} MiB: {copy['gbs']:.0f} GB/s (read + write)")
     g = torch.Generator(device=dev)
     g.manual_seed(0)
     x = torch.rand((n, n), generator=g, dtype=torch.float64, device=dev)
@@ -451,6 +455,8 @@ def run_transpose(args):
     kms = sum(d) / len(d)
     nbytes = 16 * n * n
     achieved = nbytes / (kms / 1e3) / 1e9
+    sources = kernel_sources_hash()
+    traffic, traffic_src = counted_traffic("transpose_sum", "transpose", sources)
     log(f"transpose sum {n} x {n}: {ms:.3f} ms/step, kernel {kms:.3f} ms, {achieved:.0f} GB/s")
     line = {
         "metric": "matrix elements/s for y = x + x^T, 16384 x 16384 float64",
@@ -461,7 +467,10 @@ def run_transpose(args):
         "config": {"workload": f"transpose sum: {n} x {n} float64 (the RI2 cuPy array)", "n": n},
         "roofline": {"bound": "hbm", "kernel": "transpose_sum", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "bytes_per_launch": nbytes, "avg_launch_us": round(kms * 1e3, 2)},
+                     "traffic": traffic, "traffic_source": traffic_src,
+                     "bytes_per_launch": nbytes, "avg_launch_us": round(kms * 1e3, 2)},
+        "copy_ceiling": copy,
+        "kernel_sources": sources,
     }
     if args.cpu_baseline == "on":
         import numpy as np
