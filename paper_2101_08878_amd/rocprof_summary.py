@@ -111,7 +111,8 @@ def traffic(args):
     kf, kw = _kernel_values(fetch, args.kernel), _kernel_values(write, args.kernel)
     f_kib, w_kib = sum(kf) / len(kf), sum(kw) / len(kw)
     res = {
-        "kernel": args.kernel,
+        "kernel": args.report_as or args.kernel,
+        "device_kernel": args.kernel,
         "workload": args.workload,
         "kernel_sources": kernel_sources_hash(),
         "fetch_kib_per_launch": round(f_kib, 1),
@@ -142,7 +143,8 @@ def main(argv=None):
     c = sub.add_parser("traffic")
     c.add_argument("fetch_dir")
     c.add_argument("write_dir")
-    c.add_argument("--kernel", required=True)
+    c.add_argument("--kernel", required=True, help="device kernel name (before template args)")
+    c.add_argument("--report-as", default="", help="name bench.py traces the kernel by")
     c.add_argument("--workload", required=True)
     c.add_argument("--copy-bytes", type=int, required=True)
     c.add_argument("--cmd-fetch", required=True)
