@@ -9,7 +9,10 @@
 namespace mdx {
 
 constexpr int kWave = 64;
-constexpr int kBlock = 256;            // 4 waves per workgroup
+#ifndef MDX_BLOCK
+#define MDX_BLOCK 512
+#endif
+constexpr int kBlock = MDX_BLOCK;      // threads per workgroup (8 waves)
 constexpr int kWavesPerBlock = kBlock / kWave;
 
 // ---- the hash -------------------------------------------------------------
@@ -102,7 +105,7 @@ __device__ __forceinline__ int64_t wave_sum(int64_t v)
     return v;
 }
 
-// Exclusive scan over a 256-thread block.  Returns the thread's exclusive
+// Exclusive scan over a kBlock-thread block.  Returns the thread's exclusive
 // prefix; *total receives the block sum.  Uses 4 int64 of LDS (scratch).
 __device__ __forceinline__ int64_t block_excl_scan(int64_t v, int64_t *scratch, int64_t *total)
 {

@@ -11,6 +11,7 @@
 namespace mdx {
 
 constexpr size_t kAlign = 256;
+constexpr size_t kMaxLdsBytes = 160 * 1024;  // LDS of one gfx950 CU
 
 inline size_t align_up(size_t x, size_t a = kAlign)
 {
@@ -38,13 +39,13 @@ inline Dest make_dest(int32_t P, int sbits = 0)
 }
 
 // ---- partition ------------------------------------------------------------
-// Rows per tile of the partition kernels: 256 threads x R rows.  Small P
+// Rows per tile of the partition kernels: kBlock threads x R rows.  Small P
 // keeps one tile's rows staged in LDS; large P needs LDS for its counters.
 #ifndef MDX_PART_ROWS
-#define MDX_PART_ROWS 16
+#define MDX_PART_ROWS 8
 #endif
-constexpr int kPartRowsSmall = MDX_PART_ROWS;  // tile 256 R rows, P <= kPartSmallMaxP
-constexpr int kPartRowsLarge = 4;    // tile 1024 rows
+constexpr int kPartRowsSmall = MDX_PART_ROWS;  // tile kBlock R rows, P <= kPartSmallMaxP
+constexpr int kPartRowsLarge = 2;    // tile 1024 rows (LDS holds 16-bit counts per wave and P)
 constexpr int kPartSmallMaxP = 256;
 
 inline int part_rows_per_thread(int32_t P)
@@ -84,7 +85,7 @@ hipError_t launch_partition(const void *keys, const int64_t *pay, int64_t n, int
 // is split stably into 2^bits destinations by digit_of(h, shift, bits);
 // destination (a, q) lands at [outoff[a 2^bits + q], outoff[a 2^bits + q + 1]).
 #ifndef MDX_SEG_ROWS
-#define MDX_SEG_ROWS 16
+#define MDX_SEG_ROWS 8
 #endif
 constexpr int kSegRows = MDX_SEG_ROWS;          // rows per thread
 constexpr int kSegTile = kBlock * kSegRows;     // 4096 rows per tile

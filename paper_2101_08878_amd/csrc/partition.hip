@@ -4,7 +4,7 @@
 // "Shuffle: True"): each row goes to destination p = fmix64(key) mod P, and
 // destination p's rows are packed, in input order, into [off[p], off[p+1]).
 //
-// Three passes over tiles of T = 256 * R rows:
+// Three passes over tiles of T = kBlock * R rows (512 x 8 = 4096):
 //   part_hist       keys only: per-tile counts per destination (LDS atomics)
 //   part_scan_tiles per destination, exclusive prefix over tiles (in place)
 //   part_offsets    exclusive prefix over destinations -> off[0..P]
@@ -119,8 +119,8 @@ __host__ __device__ inline ScatterLds scatter_lds(int T, int P, int key_bytes)
     o = al16(o + (size_t)T * key_bytes);
     L.stage_p = o;
     o = al16(o + (size_t)T * 2);
-    L.whist = o;
-    o = al16(o + (size_t)kWavesPerBlock * P * 4);
+    L.whist = o;  // 16-bit counts: a tile holds at most 4096 rows
+    o = al16(o + (size_t)kWavesPerBlock * P * 2);
     L.tstart = o;
     o = al16(o + (size_t)P * 4);
     L.gbase = o;
@@ -147,7 +147,7 @@ __device__ inline void lds_excl_scan_u32(uint32_t *a, int P, int64_t *scratch)
     __syncthreads();
 }
 
-// Stable scatter of one tile, rows [row0, row_end) (at most 256 R of them).
+// Stable scatter of one tile, rows [row0, row_end) (at most kBlock R of them).
 // dfn(h) gives a row's destination in [0, D); base_of(d) the output position
 // of the tile's first row with destination d.  Wave w owns the contiguous
 // rows [row0 + 64 R w, row0 + 64 R (w+1)); step c reads 64 consecutive rows.
@@ -159,11 +159,12 @@ __device__ __forceinline__ void scatter_tile(const K *__restrict__ keys,
                                              int64_t *__restrict__ pay_out, unsigned char *smem)
 {
     constexpr int T = kBlock * R;
+    static_assert(T <= 65535, "per-wave tile counts are 16-bit");
     const ScatterLds L = scatter_lds(T, D, (int)sizeof(K));
     int64_t *stage_v = (int64_t *)(smem + L.stage_v);
     K *stage_k = (K *)(smem + L.stage_k);
     uint16_t *stage_p = (uint16_t *)(smem + L.stage_p);
-    uint32_t *whist = (uint32_t *)(smem + L.whist);
+    uint16_t *whist = (uint16_t *)(smem + L.whist);
     uint32_t *tstart = (uint32_t *)(smem + L.tstart);
     int64_t *gbase = (int64_t *)(smem + L.gbase);
     int64_t *scratch = (int64_t *)(smem + L.scratch);
@@ -187,7 +188,7 @@ __device__ __forceinline__ void scatter_tile(const K *__restrict__ keys,
     __syncthreads();
 
     // Rank every row among the earlier rows of its wave with its destination.
-    uint32_t *wh = whist + w * D;
+    uint16_t *wh = whist + w * D;
     uint32_t pr[R], rk[R];
 #pragma unroll
     for (int c = 0; c < R; ++c) {
@@ -205,7 +206,7 @@ __device__ __forceinline__ void scatter_tile(const K *__restrict__ keys,
         if (valid)
             prev = wh[p];
         if (valid && rank == 0)
-            wh[p] = prev + (uint32_t)__popcll(m);
+            wh[p] = (uint16_t)(prev + (uint32_t)__popcll(m));
         pr[c] = valid ? p : 0xffffffffu;
         rk[c] = prev + rank;
     }
@@ -217,7 +218,7 @@ __device__ __forceinline__ void scatter_tile(const K *__restrict__ keys,
 #pragma unroll
         for (int ww = 0; ww < kWavesPerBlock; ++ww) {
             const uint32_t c = whist[ww * D + p];
-            whist[ww * D + p] = acc;
+            whist[ww * D + p] = (uint16_t)acc;
             acc += c;
         }
         tstart[p] = acc;
@@ -228,7 +229,7 @@ __device__ __forceinline__ void scatter_tile(const K *__restrict__ keys,
         const uint32_t t0 = tstart[p];
 #pragma unroll
         for (int ww = 0; ww < kWavesPerBlock; ++ww)
-            whist[ww * D + p] += t0;
+            whist[ww * D + p] = (uint16_t)(whist[ww * D + p] + t0);
     }
     __syncthreads();
 
@@ -440,6 +441,8 @@ hipError_t run_partition(const K *keys, const int64_t *pay, int64_t n, int32_t P
     hipLaunchKernelGGL(part_offsets, dim3(1), dim3(kBlock), 0, s, totals, D, off);
     if (L.ntiles > 0) {
         const size_t lds = scatter_lds(kBlock * R, D, (int)sizeof(K)).total;
+        if (lds > kMaxLdsBytes)
+            return hipErrorInvalidValue;  // cannot happen for D <= MDX_MAX_P
         hipError_t e = hipFuncSetAttribute((const void *)part_scatter<K, R>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess)
@@ -487,6 +490,8 @@ hipError_t launch_seg_partition(const void *keys, const int64_t *pay, int64_t n,
     const int ns = (int)nseg;
     hipLaunchKernelGGL(seg_plan, dim3(1), dim3(kBlock), 0, s, segoff, ns, tile_start, chunk_start);
     const size_t lds = scatter_lds(kSegTile, 1 << bits, key_bytes).total;
+    if (lds > kMaxLdsBytes)
+        return hipErrorInvalidValue;  // cannot happen for bits <= 8
     if (key_bytes == 8) {
         hipLaunchKernelGGL(seg_hist<int64_t>, dim3((unsigned)L.max_chunks), dim3(kBlock), 0, s,
                            (const int64_t *)keys, segoff, ns, tile_start, chunk_start, shift, bits,
