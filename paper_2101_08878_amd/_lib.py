@@ -114,8 +114,8 @@ ABI_FUNCTIONS = [
     "mdx_transpose_sum",
     "mdx_trace_kernel",
 ]
-TRACEABLE_KERNELS = ["part_hist", "part_scatter", "seg_scatter", "rj_join", "tbl_init",
-                     "tbl_insert", "probe_chain", "probe_expand", "transpose_sum"]
+TRACEABLE_KERNELS = ["part_hist", "part_scatter", "seg_hist", "seg_scatter", "rj_join",
+                     "tbl_init", "tbl_insert", "probe_chain", "probe_expand", "transpose_sum"]
 
 
 class MdxError(RuntimeError):

@@ -167,7 +167,7 @@ int32_t mdx_trace_kernel(const char *kernel, hipEvent_t *h_starts, hipEvent_t *h
     }
     static const char *known[] = {"part_hist", "part_scatter", "tbl_init",
                                   "tbl_insert", "probe_chain", "probe_expand",
-                                  "seg_scatter", "rj_join", "transpose_sum"};
+                                  "seg_hist", "seg_scatter", "rj_join", "transpose_sum"};
     bool ok = false;
     for (const char *k : known)
         ok |= std::string(k) == kernel;
@@ -228,7 +228,7 @@ int32_t mdx_hash_partition(const void *d_keys, const int64_t *d_payload, int64_t
         return fail(MDX_ERR_WORKSPACE, "mdx_hash_partition: workspace needs " +
                                            std::to_string(L.bytes) + " bytes");
     hipError_t e = launch_partition(d_keys, d_payload, n, key_type, P, 0, d_keys_out, d_payload_out,
-                                    d_offsets, d_ws, stream);
+                                    d_offsets, nullptr, 0, 0, d_ws, stream);
     return e == hipSuccess ? MDX_OK : hip_fail(e, W);
 }
 
@@ -448,8 +448,8 @@ struct MergeLayout {
     TableLayout tl;
     ProbeLayout ql;
     size_t partL_off, partR_off, lk1_off, lv1_off, rk1_off, rv1_off, offAL_off, offAR_off,
-        offPL_off, offPR_off, segL_off, segR_off, lk2_off, lv2_off, rk2_off, rv2_off, subL_off,
-        subR_off, rjoin_off, table_off, probe_off, bytes;
+        offPL_off, offPR_off, digL_off, digR_off, segL_off, segR_off, lk2_off, lv2_off, rk2_off,
+        rv2_off, subL_off, subR_off, rjoin_off, table_off, probe_off, bytes;
 };
 
 MergeLayout merge_layout(int64_t nL, int64_t nR, int32_t P, int32_t kt)
@@ -482,6 +482,8 @@ MergeLayout merge_layout(int64_t nL, int64_t nR, int32_t P, int32_t kt)
     take(M.offAR_off, (size_t)(M.nA + 1) * 8);
     take(M.offPL_off, (size_t)(P + 1) * 8);
     take(M.offPR_off, (size_t)(P + 1) * 8);
+    take(M.digL_off, two ? kL : 0);
+    take(M.digR_off, two ? kR : 0);
     take(M.segL_off, two ? M.sl.bytes : 0);
     take(M.segR_off, two ? M.sr.bytes : 0);
     take(M.lk2_off, two ? kL * kt : 0);
@@ -564,25 +566,31 @@ static hipError_t enqueue_merge(const mdx_merge_desc &d, void *d_ws, hipStream_t
     o.cap = d.out_capacity;
     o.offsets = d.d_out_offsets;
 
-    // 1. partition both tables by (partition, top q1bits of the hash)
+    // 1. partition both tables by (partition, top q1bits of the hash); with a
+    // second pass, every output row's next q2bits go beside it as a byte
+    const bool two = pl.q2bits > 0;
+    uint8_t *digL = two ? (uint8_t *)(b + M.digL_off) : nullptr;
+    uint8_t *digR = two ? (uint8_t *)(b + M.digR_off) : nullptr;
     hipError_t e = launch_partition(d.d_left_keys, d.d_left_payload, n_left, key_type, P,
-                                    pl.q1bits, lk1, lv1, offAL, b + M.partL_off, stream);
+                                    pl.q1bits, lk1, lv1, offAL, digL, pl.q1bits, pl.q2bits,
+                                    b + M.partL_off, stream);
     if (e == hipSuccess)
         e = launch_partition(d.d_right_keys, d.d_right_payload, n_right, key_type, P, pl.q1bits,
-                             rk1, rv1, offAR, b + M.partR_off, stream);
+                             rk1, rv1, offAR, digR, pl.q1bits, pl.q2bits, b + M.partR_off,
+                             stream);
 
     // 2. split every first-pass bucket by the next q2bits: sub-buckets
     const void *lk = lk1, *rk = rk1;
     const int64_t *lv = lv1, *rv = rv1, *subL = offAL, *subR = offAR;
-    if (pl.q2bits > 0 && e == hipSuccess) {
+    if (two && e == hipSuccess) {
         void *lk2 = b + M.lk2_off, *rk2 = b + M.rk2_off;
         int64_t *lv2 = (int64_t *)(b + M.lv2_off), *rv2 = (int64_t *)(b + M.rv2_off);
         int64_t *sL = (int64_t *)(b + M.subL_off), *sR = (int64_t *)(b + M.subR_off);
-        e = launch_seg_partition(lk1, lv1, n_left, key_type, offAL, nA, pl.q1bits, pl.q2bits, lk2,
-                                 lv2, sL, b + M.segL_off, nullptr, stream);
+        e = launch_seg_partition(lk1, lv1, digL, n_left, key_type, offAL, nA, pl.q1bits,
+                                 pl.q2bits, lk2, lv2, sL, b + M.segL_off, nullptr, stream);
         if (e == hipSuccess)
-            e = launch_seg_partition(rk1, rv1, n_right, key_type, offAR, nA, pl.q1bits, pl.q2bits,
-                                     rk2, rv2, sR, b + M.segR_off, nullptr, stream);
+            e = launch_seg_partition(rk1, rv1, digR, n_right, key_type, offAR, nA, pl.q1bits,
+                                     pl.q2bits, rk2, rv2, sR, b + M.segR_off, nullptr, stream);
         lk = lk2;
         rk = rk2;
         lv = lv2;

@@ -75,10 +75,12 @@ inline PartLayout part_layout(int64_t n, int32_t P)
 }
 
 // Stable partition into make_dest(P, sbits).ndest destinations; off has
-// ndest + 1 entries; ws holds part_layout(n, ndest).bytes.
+// ndest + 1 entries; ws holds part_layout(n, ndest).bytes.  With dig_out
+// (n bytes), every output row's digit_of(h, dshift, dbits) is written beside
+// it, for the histogram of a following segmented pass.
 hipError_t launch_partition(const void *keys, const int64_t *pay, int64_t n, int key_bytes,
                             int32_t P, int sbits, void *keys_out, int64_t *pay_out, int64_t *off,
-                            void *ws, hipStream_t s);
+                            uint8_t *dig_out, int dshift, int dbits, void *ws, hipStream_t s);
 
 // ---- segmented partition (second split of the join) -------------------------
 // Segment a (rows [segoff[a], segoff[a+1]) of an already partitioned table)
@@ -116,11 +118,12 @@ inline SegLayout seg_layout(int64_t n, int64_t nseg, int bits)
     return L;
 }
 
+// dig holds every row's digit_of(h, shift, bits), one byte per row (bits <= 8).
 // gate (optional, device): when *gate == 0 the scatter is skipped.
-hipError_t launch_seg_partition(const void *keys, const int64_t *pay, int64_t n, int key_bytes,
-                                const int64_t *segoff, int64_t nseg, int shift, int bits,
-                                void *keys_out, int64_t *pay_out, int64_t *outoff, void *ws,
-                                const int32_t *gate, hipStream_t s);
+hipError_t launch_seg_partition(const void *keys, const int64_t *pay, const uint8_t *dig,
+                                int64_t n, int key_bytes, const int64_t *segoff, int64_t nseg,
+                                int shift, int bits, void *keys_out, int64_t *pay_out,
+                                int64_t *outoff, void *ws, const int32_t *gate, hipStream_t s);
 
 // ---- radix join (LDS tables per sub-bucket) ---------------------------------
 // Sub-bucket s of S = P 2^qbits holds build rows [subL[s], subL[s+1]) and

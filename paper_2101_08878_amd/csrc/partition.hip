@@ -30,7 +30,9 @@ __global__ __launch_bounds__(kBlock) void part_hist(const K *__restrict__ keys, 
     const int P = d.ndest;  // destinations
     for (int p = tid; p < P; p += kBlock)
         hist[p] = 0;
-    const int64_t tile = blockIdx.x;
+    // XCD-contiguous tile order: the counts of neighbouring tiles share cache
+    // lines, which then fill in one L2
+    const int64_t tile = tile_of_block(blockIdx.x, gridDim.x);
     const int64_t row0 = tile * (int64_t)(kBlock * R);
     K k[R];
 #pragma unroll
@@ -51,33 +53,58 @@ __global__ __launch_bounds__(kBlock) void part_hist(const K *__restrict__ keys, 
 }
 
 // Block p: exclusive prefix of cnt[p][0..ntiles) in place, total to totals[p].
+// Rounds of kBlock * kScanV counts: loaded and stored with consecutive lanes
+// on consecutive counts, staged in LDS so that thread t sums the kScanV
+// consecutive counts [t kScanV, (t+1) kScanV) (rows padded by one count, so
+// those reads spread over the banks), then one block scan of the sums.
+constexpr int kScanV = 16;
+constexpr int kScanChunk = kBlock * kScanV;
+
+__device__ __forceinline__ int scan_slot(int e)
+{
+    return e + e / kScanV;
+}
+
 __global__ __launch_bounds__(kBlock) void part_scan_tiles(int64_t *__restrict__ cnt, int64_t ntiles,
                                                           int64_t *__restrict__ totals)
 {
     __shared__ int64_t scratch[kWavesPerBlock];
-    constexpr int V = 8;
+    __shared__ int64_t buf[kScanChunk + kBlock];
+    const int tid = threadIdx.x;
     int64_t *row = cnt + (int64_t)blockIdx.x * ntiles;
     int64_t carry = 0;
-    for (int64_t base = 0; base < ntiles; base += (int64_t)kBlock * V) {
-        const int64_t i0 = base + (int64_t)threadIdx.x * V;
-        int64_t v[V];
-        int64_t s = 0;
+    for (int64_t base = 0; base < ntiles; base += kScanChunk) {
+        const int m = (int)(ntiles - base < kScanChunk ? ntiles - base : kScanChunk);
 #pragma unroll
-        for (int j = 0; j < V; ++j) {
-            v[j] = (i0 + j < ntiles) ? row[i0 + j] : 0;
-            s += v[j];
+        for (int j = 0; j < kScanV; ++j) {
+            const int e = j * kBlock + tid;
+            buf[scan_slot(e)] = e < m ? row[base + e] : 0;
+        }
+        __syncthreads();
+        int64_t v[kScanV], sum = 0;
+#pragma unroll
+        for (int i = 0; i < kScanV; ++i) {
+            v[i] = buf[scan_slot(tid * kScanV + i)];
+            sum += v[i];
         }
         int64_t tot;
-        int64_t run = carry + block_excl_scan(s, scratch, &tot);
+        int64_t run = carry + block_excl_scan(sum, scratch, &tot);
 #pragma unroll
-        for (int j = 0; j < V; ++j) {
-            if (i0 + j < ntiles)
-                row[i0 + j] = run;
-            run += v[j];
+        for (int i = 0; i < kScanV; ++i) {
+            buf[scan_slot(tid * kScanV + i)] = run;
+            run += v[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kScanV; ++j) {
+            const int e = j * kBlock + tid;
+            if (e < m)
+                row[base + e] = buf[scan_slot(e)];
         }
         carry += tot;
+        __syncthreads();  // buf is refilled by the next round
     }
-    if (threadIdx.x == 0)
+    if (tid == 0)
         totals[blockIdx.x] = carry;
 }
 
@@ -156,7 +183,9 @@ __device__ __forceinline__ void scatter_tile(const K *__restrict__ keys,
                                              const int64_t *__restrict__ pay, int64_t row0,
                                              int64_t row_end, int D, int nbits, DestFn dfn,
                                              BaseFn base_of, K *__restrict__ keys_out,
-                                             int64_t *__restrict__ pay_out, unsigned char *smem)
+                                             int64_t *__restrict__ pay_out, unsigned char *smem,
+                                             uint8_t *__restrict__ dig_out = nullptr,
+                                             int dshift = 0, int dbits = 0)
 {
     constexpr int T = kBlock * R;
     static_assert(T <= 65535, "per-wave tile counts are 16-bit");
@@ -255,6 +284,8 @@ __device__ __forceinline__ void scatter_tile(const K *__restrict__ keys,
         // bytes written, 26% slower at a fan-out of 128.
         keys_out[dst] = stage_k[s];
         pay_out[dst] = stage_v[s];
+        if (dig_out)
+            dig_out[dst] = (uint8_t)digit_of(fmix64(key_bits(stage_k[s])), dshift, dbits);
     }
 }
 
@@ -262,14 +293,16 @@ template <typename K, int R>
 __global__ __launch_bounds__(kBlock) void part_scatter(
     const K *__restrict__ keys, const int64_t *__restrict__ pay, int64_t n, Dest d,
     const int64_t *__restrict__ off, const int64_t *__restrict__ pre, int64_t ntiles,
-    K *__restrict__ keys_out, int64_t *__restrict__ pay_out)
+    K *__restrict__ keys_out, int64_t *__restrict__ pay_out, uint8_t *__restrict__ dig_out,
+    int dshift, int dbits)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int64_t tile = tile_of_block(blockIdx.x, gridDim.x);
     scatter_tile<K, R>(
         keys, pay, tile * (int64_t)(kBlock * R), n, d.ndest, d.nbits,
         [&](uint64_t h) { return dest_of(h, d); },
-        [&](int p) { return off[p] + pre[(int64_t)p * ntiles + tile]; }, keys_out, pay_out, smem);
+        [&](int p) { return off[p] + pre[(int64_t)p * ntiles + tile]; }, keys_out, pay_out, smem,
+        dig_out, dshift, dbits);
 }
 
 // ---- segmented partition -------------------------------------------------------
@@ -309,51 +342,49 @@ __global__ __launch_bounds__(kBlock) void seg_plan(const int64_t *__restrict__ s
 }
 
 // Block = chunk: per-tile digit counts, stored as the exclusive prefix over
-// the chunk's earlier tiles; chunk totals to csum.
-template <typename K>
+// the chunk's earlier tiles; chunk totals to csum.  The digits are the bytes
+// the first pass wrote beside its output rows, so this pass reads one byte
+// per row instead of the key.  All of the chunk's bytes are loaded at once,
+// then counted into one LDS histogram per tile.
 __global__ __launch_bounds__(kBlock) void seg_hist(
-    const K *__restrict__ keys, const int64_t *__restrict__ segoff, int nseg,
-    const int64_t *__restrict__ tile_start, const int64_t *__restrict__ chunk_start, int shift,
-    int bits, uint32_t *__restrict__ cnt, int64_t *__restrict__ csum)
+    const uint8_t *__restrict__ dig, const int64_t *__restrict__ segoff, int nseg,
+    const int64_t *__restrict__ tile_start, const int64_t *__restrict__ chunk_start, int bits,
+    uint32_t *__restrict__ cnt, int64_t *__restrict__ csum)
 {
-    __shared__ uint32_t hist[kSegMaxDest], run[kSegMaxDest];
+    __shared__ uint32_t hist[kSegChunkTiles][kSegMaxDest];
+    constexpr uint32_t kNone = 0xffffffffu;
     const int64_t c = blockIdx.x;
     if (c >= chunk_start[nseg])
         return;
     const int D = 1 << bits, tid = threadIdx.x;
     const int a = upper_index(chunk_start, 0, nseg, c);
+    const int64_t s1 = segoff[a + 1];
     const int64_t t0 = tile_start[a] + (c - chunk_start[a]) * kSegChunkTiles;
-    const int64_t t1 = t0 + kSegChunkTiles < tile_start[a + 1] ? t0 + kSegChunkTiles
-                                                                : tile_start[a + 1];
-    for (int q = tid; q < D; q += kBlock)
-        run[q] = 0;
-    for (int64_t t = t0; t < t1; ++t) {
-        for (int q = tid; q < D; q += kBlock)
-            hist[q] = 0;
-        const int64_t r0 = segoff[a] + (t - tile_start[a]) * kSegTile;
-        const int64_t r1 = r0 + kSegTile < segoff[a + 1] ? r0 + kSegTile : segoff[a + 1];
-        K k[kSegRows];
+    const int nt = (int)(t0 + kSegChunkTiles < tile_start[a + 1] ? kSegChunkTiles
+                                                                  : tile_start[a + 1] - t0);
+    const int64_t r0 = segoff[a] + (t0 - tile_start[a]) * kSegTile;  // chunk's first row
+    for (int i = tid; i < kSegChunkTiles * kSegMaxDest; i += kBlock)
+        (&hist[0][0])[i] = 0;
+    uint32_t d[kSegChunkTiles * kSegRows];
 #pragma unroll
-        for (int j = 0; j < kSegRows; ++j) {
-            const int64_t r = r0 + (int64_t)j * kBlock + tid;
-            k[j] = r < r1 ? __builtin_nontemporal_load(keys + r) : K(0);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < kSegRows; ++j) {
-            const int64_t r = r0 + (int64_t)j * kBlock + tid;
-            if (r < r1)
-                atomicAdd(&hist[digit_of(fmix64(key_bits(k[j])), shift, bits)], 1u);
-        }
-        __syncthreads();
-        for (int q = tid; q < D; q += kBlock) {
-            cnt[t * D + q] = run[q];
-            run[q] += hist[q];
-        }
-        __syncthreads();
+    for (int j = 0; j < kSegChunkTiles * kSegRows; ++j) {
+        const int64_t r = r0 + (int64_t)j * kBlock + tid;  // tile j / kSegRows
+        d[j] = r < s1 ? (uint32_t)__builtin_nontemporal_load(dig + r) : kNone;
     }
-    for (int q = tid; q < D; q += kBlock)
-        csum[c * D + q] = run[q];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kSegChunkTiles * kSegRows; ++j)
+        if (d[j] != kNone)
+            atomicAdd(&hist[j / kSegRows][d[j]], 1u);
+    __syncthreads();
+    for (int q = tid; q < D; q += kBlock) {
+        uint32_t run = 0;
+        for (int t = 0; t < nt; ++t) {
+            cnt[(t0 + t) * D + q] = run;
+            run += hist[t][q];
+        }
+        csum[c * D + q] = run;
+    }
 }
 
 // Block = segment: chunk totals -> exclusive prefix over the segment's chunks
@@ -423,7 +454,8 @@ __global__ __launch_bounds__(kBlock) void seg_scatter(
 
 template <typename K, int R>
 hipError_t run_partition(const K *keys, const int64_t *pay, int64_t n, int32_t P, int sbits,
-                         K *keys_out, int64_t *pay_out, int64_t *off, void *ws, hipStream_t s)
+                         K *keys_out, int64_t *pay_out, int64_t *off, uint8_t *dig_out,
+                         int dshift, int dbits, void *ws, hipStream_t s)
 {
     const Dest d = make_dest(P, sbits);
     const int D = d.ndest;
@@ -449,7 +481,8 @@ hipError_t run_partition(const K *keys, const int64_t *pay, int64_t n, int32_t P
             return e;
         trace_begin("part_scatter", s);
         hipLaunchKernelGGL((part_scatter<K, R>), dim3((unsigned)L.ntiles), dim3(kBlock), lds, s,
-                           keys, pay, n, d, off, cnt, L.ntiles, keys_out, pay_out);
+                           keys, pay, n, d, off, cnt, L.ntiles, keys_out, pay_out, dig_out,
+                           dshift, dbits);
         trace_end("part_scatter", s);
     }
     return hipGetLastError();
@@ -459,27 +492,31 @@ hipError_t run_partition(const K *keys, const int64_t *pay, int64_t n, int32_t P
 
 hipError_t launch_partition(const void *keys, const int64_t *pay, int64_t n, int key_bytes,
                             int32_t P, int sbits, void *keys_out, int64_t *pay_out, int64_t *off,
-                            void *ws, hipStream_t s)
+                            uint8_t *dig_out, int dshift, int dbits, void *ws, hipStream_t s)
 {
     const int R = part_rows_per_thread(P << sbits);
     if (key_bytes == 8) {
         if (R == kPartRowsSmall)
             return run_partition<int64_t, kPartRowsSmall>((const int64_t *)keys, pay, n, P, sbits,
-                                                          (int64_t *)keys_out, pay_out, off, ws, s);
+                                                          (int64_t *)keys_out, pay_out, off,
+                                                          dig_out, dshift, dbits, ws, s);
         return run_partition<int64_t, kPartRowsLarge>((const int64_t *)keys, pay, n, P, sbits,
-                                                      (int64_t *)keys_out, pay_out, off, ws, s);
+                                                      (int64_t *)keys_out, pay_out, off, dig_out,
+                                                      dshift, dbits, ws, s);
     }
     if (R == kPartRowsSmall)
         return run_partition<int32_t, kPartRowsSmall>((const int32_t *)keys, pay, n, P, sbits,
-                                                      (int32_t *)keys_out, pay_out, off, ws, s);
+                                                      (int32_t *)keys_out, pay_out, off, dig_out,
+                                                      dshift, dbits, ws, s);
     return run_partition<int32_t, kPartRowsLarge>((const int32_t *)keys, pay, n, P, sbits,
-                                                  (int32_t *)keys_out, pay_out, off, ws, s);
+                                                  (int32_t *)keys_out, pay_out, off, dig_out,
+                                                  dshift, dbits, ws, s);
 }
 
-hipError_t launch_seg_partition(const void *keys, const int64_t *pay, int64_t n, int key_bytes,
-                                const int64_t *segoff, int64_t nseg, int shift, int bits,
-                                void *keys_out, int64_t *pay_out, int64_t *outoff, void *ws,
-                                const int32_t *gate, hipStream_t s)
+hipError_t launch_seg_partition(const void *keys, const int64_t *pay, const uint8_t *dig,
+                                int64_t n, int key_bytes, const int64_t *segoff, int64_t nseg,
+                                int shift, int bits, void *keys_out, int64_t *pay_out,
+                                int64_t *outoff, void *ws, const int32_t *gate, hipStream_t s)
 {
     const SegLayout L = seg_layout(n, nseg, bits);
     char *b = (char *)ws;
@@ -492,15 +529,10 @@ hipError_t launch_seg_partition(const void *keys, const int64_t *pay, int64_t n,
     const size_t lds = scatter_lds(kSegTile, 1 << bits, key_bytes).total;
     if (lds > kMaxLdsBytes)
         return hipErrorInvalidValue;  // cannot happen for bits <= 8
-    if (key_bytes == 8) {
-        hipLaunchKernelGGL(seg_hist<int64_t>, dim3((unsigned)L.max_chunks), dim3(kBlock), 0, s,
-                           (const int64_t *)keys, segoff, ns, tile_start, chunk_start, shift, bits,
-                           cnt, csum);
-    } else {
-        hipLaunchKernelGGL(seg_hist<int32_t>, dim3((unsigned)L.max_chunks), dim3(kBlock), 0, s,
-                           (const int32_t *)keys, segoff, ns, tile_start, chunk_start, shift, bits,
-                           cnt, csum);
-    }
+    trace_begin("seg_hist", s);
+    hipLaunchKernelGGL(seg_hist, dim3((unsigned)L.max_chunks), dim3(kBlock), 0, s, dig, segoff,
+                       ns, tile_start, chunk_start, bits, cnt, csum);
+    trace_end("seg_hist", s);
     hipLaunchKernelGGL(seg_scan, dim3((unsigned)ns), dim3(kBlock), 0, s, segoff, ns, chunk_start,
                        bits, csum, outoff);
     hipError_t e;
