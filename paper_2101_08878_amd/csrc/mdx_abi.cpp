@@ -227,8 +227,8 @@ int32_t mdx_hash_partition(const void *d_keys, const int64_t *d_payload, int64_t
     if (ws_bytes < L.bytes)
         return fail(MDX_ERR_WORKSPACE, "mdx_hash_partition: workspace needs " +
                                            std::to_string(L.bytes) + " bytes");
-    hipError_t e = launch_partition(d_keys, d_payload, n, key_type, P, 0, d_keys_out, d_payload_out,
-                                    d_offsets, nullptr, 0, 0, d_ws, stream);
+    const PartArgs t = {d_keys, d_payload, n, d_keys_out, d_payload_out, d_offsets, nullptr, d_ws};
+    hipError_t e = launch_partition(&t, 1, key_type, P, 0, 0, 0, stream);
     return e == hipSuccess ? MDX_OK : hip_fail(e, W);
 }
 
@@ -571,13 +571,10 @@ static hipError_t enqueue_merge(const mdx_merge_desc &d, void *d_ws, hipStream_t
     const bool two = pl.q2bits > 0;
     uint8_t *digL = two ? (uint8_t *)(b + M.digL_off) : nullptr;
     uint8_t *digR = two ? (uint8_t *)(b + M.digR_off) : nullptr;
-    hipError_t e = launch_partition(d.d_left_keys, d.d_left_payload, n_left, key_type, P,
-                                    pl.q1bits, lk1, lv1, offAL, digL, pl.q1bits, pl.q2bits,
-                                    b + M.partL_off, stream);
-    if (e == hipSuccess)
-        e = launch_partition(d.d_right_keys, d.d_right_payload, n_right, key_type, P, pl.q1bits,
-                             rk1, rv1, offAR, digR, pl.q1bits, pl.q2bits, b + M.partR_off,
-                             stream);
+    const PartArgs pt[2] = {
+        {d.d_left_keys, d.d_left_payload, n_left, lk1, lv1, offAL, digL, b + M.partL_off},
+        {d.d_right_keys, d.d_right_payload, n_right, rk1, rv1, offAR, digR, b + M.partR_off}};
+    hipError_t e = launch_partition(pt, 2, key_type, P, pl.q1bits, pl.q1bits, pl.q2bits, stream);
 
     // 2. split every first-pass bucket by the next q2bits: sub-buckets
     const void *lk = lk1, *rk = rk1;
@@ -586,11 +583,9 @@ static hipError_t enqueue_merge(const mdx_merge_desc &d, void *d_ws, hipStream_t
         void *lk2 = b + M.lk2_off, *rk2 = b + M.rk2_off;
         int64_t *lv2 = (int64_t *)(b + M.lv2_off), *rv2 = (int64_t *)(b + M.rv2_off);
         int64_t *sL = (int64_t *)(b + M.subL_off), *sR = (int64_t *)(b + M.subR_off);
-        e = launch_seg_partition(lk1, lv1, digL, n_left, key_type, offAL, nA, pl.q1bits,
-                                 pl.q2bits, lk2, lv2, sL, b + M.segL_off, nullptr, stream);
-        if (e == hipSuccess)
-            e = launch_seg_partition(rk1, rv1, digR, n_right, key_type, offAR, nA, pl.q1bits,
-                                     pl.q2bits, rk2, rv2, sR, b + M.segR_off, nullptr, stream);
+        const SegArgs st[2] = {{lk1, lv1, digL, n_left, offAL, lk2, lv2, sL, b + M.segL_off},
+                               {rk1, rv1, digR, n_right, offAR, rk2, rv2, sR, b + M.segR_off}};
+        e = launch_seg_partition(st, 2, key_type, nA, pl.q1bits, pl.q2bits, stream);
         lk = lk2;
         rk = rk2;
         lv = lv2;

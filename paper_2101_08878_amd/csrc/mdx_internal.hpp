@@ -74,13 +74,26 @@ inline PartLayout part_layout(int64_t n, int32_t P)
     return L;
 }
 
-// Stable partition into make_dest(P, sbits).ndest destinations; off has
-// ndest + 1 entries; ws holds part_layout(n, ndest).bytes.  With dig_out
-// (n bytes), every output row's digit_of(h, dshift, dbits) is written beside
-// it, for the histogram of a following segmented pass.
-hipError_t launch_partition(const void *keys, const int64_t *pay, int64_t n, int key_bytes,
-                            int32_t P, int sbits, void *keys_out, int64_t *pay_out, int64_t *off,
-                            uint8_t *dig_out, int dshift, int dbits, void *ws, hipStream_t s);
+// One table of a partition launch: stable partition into
+// make_dest(P, sbits).ndest destinations; off has ndest + 1 entries; ws holds
+// part_layout(n, ndest).bytes.  With dig (n bytes), every output row's
+// digit_of(h, dshift, dbits) is written beside it, for the histogram of a
+// following segmented pass.
+struct PartArgs {
+    const void *keys;
+    const int64_t *pay;
+    int64_t n;
+    void *keys_out;
+    int64_t *pay_out;
+    int64_t *off;
+    uint8_t *dig;
+    void *ws;
+};
+
+// Partition 1 or 2 tables (same key width and destinations) with one set of
+// launches.
+hipError_t launch_partition(const PartArgs *tables, int ntables, int key_bytes, int32_t P,
+                            int sbits, int dshift, int dbits, hipStream_t s);
 
 // ---- segmented partition (second split of the join) -------------------------
 // Segment a (rows [segoff[a], segoff[a+1]) of an already partitioned table)
@@ -118,12 +131,25 @@ inline SegLayout seg_layout(int64_t n, int64_t nseg, int bits)
     return L;
 }
 
-// dig holds every row's digit_of(h, shift, bits), one byte per row (bits <= 8).
-// gate (optional, device): when *gate == 0 the scatter is skipped.
-hipError_t launch_seg_partition(const void *keys, const int64_t *pay, const uint8_t *dig,
-                                int64_t n, int key_bytes, const int64_t *segoff, int64_t nseg,
-                                int shift, int bits, void *keys_out, int64_t *pay_out,
-                                int64_t *outoff, void *ws, const int32_t *gate, hipStream_t s);
+// One table of a segmented launch: dig holds every row's
+// digit_of(h, shift, bits), one byte per row (bits <= 8); segoff has nseg + 1
+// entries, outoff nseg 2^bits + 1; ws holds seg_layout(n, nseg, bits).bytes.
+struct SegArgs {
+    const void *keys;
+    const int64_t *pay;
+    const uint8_t *dig;
+    int64_t n;
+    const int64_t *segoff;
+    void *keys_out;
+    int64_t *pay_out;
+    int64_t *outoff;
+    void *ws;
+};
+
+// Split 1 or 2 tables (same key width, segment count and digits) with one
+// set of launches.
+hipError_t launch_seg_partition(const SegArgs *tables, int ntables, int key_bytes, int64_t nseg,
+                                int shift, int bits, hipStream_t s);
 
 // ---- radix join (LDS tables per sub-bucket) ---------------------------------
 // Sub-bucket s of S = P 2^qbits holds build rows [subL[s], subL[s+1]) and

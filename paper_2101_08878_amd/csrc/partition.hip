@@ -21,9 +21,51 @@
 namespace mdx {
 namespace {
 
+// ---- one or two tables per launch -------------------------------------------
+// A merge partitions its build and probe tables with the same destinations,
+// so each step runs once for both: per-tile grids cover the first table's
+// tiles, then the second's (the XCD-contiguous order runs over the combined
+// range); per-destination and per-segment grids take one block range per
+// table.  A single table is the pair with an empty second table.
+template <typename K>
+struct PartTable {
+    const K *keys;
+    const int64_t *pay;
+    int64_t n, ntiles;
+    K *keys_out;
+    int64_t *pay_out;
+    int64_t *off;     // [D + 1]
+    uint8_t *dig;     // optional: one digit byte per output row
+    int64_t *cnt;     // [D][ntiles]: counts, then exclusive prefixes
+    int64_t *totals;  // [D]
+};
+
+template <typename K>
+struct PartPair {
+    PartTable<K> t[2];
+};
+
+// Table `second` of a pair, by field-wise selects on the kernel arguments.
+template <typename K>
+__device__ __forceinline__ PartTable<K> pick(const PartPair<K> &T, bool second)
+{
+    const PartTable<K> &a = T.t[0], &b = T.t[1];
+    PartTable<K> r;
+    r.keys = second ? b.keys : a.keys;
+    r.pay = second ? b.pay : a.pay;
+    r.n = second ? b.n : a.n;
+    r.ntiles = second ? b.ntiles : a.ntiles;
+    r.keys_out = second ? b.keys_out : a.keys_out;
+    r.pay_out = second ? b.pay_out : a.pay_out;
+    r.off = second ? b.off : a.off;
+    r.dig = second ? b.dig : a.dig;
+    r.cnt = second ? b.cnt : a.cnt;
+    r.totals = second ? b.totals : a.totals;
+    return r;
+}
+
 template <typename K, int R>
-__global__ __launch_bounds__(kBlock) void part_hist(const K *__restrict__ keys, int64_t n, Dest d,
-                                                    int64_t *__restrict__ cnt, int64_t ntiles)
+__global__ __launch_bounds__(kBlock) void part_hist(PartPair<K> T, Dest d)
 {
     extern __shared__ uint32_t hist[];
     const int tid = threadIdx.x;
@@ -32,24 +74,27 @@ __global__ __launch_bounds__(kBlock) void part_hist(const K *__restrict__ keys, 
         hist[p] = 0;
     // XCD-contiguous tile order: the counts of neighbouring tiles share cache
     // lines, which then fill in one L2
-    const int64_t tile = tile_of_block(blockIdx.x, gridDim.x);
+    const int64_t g = tile_of_block(blockIdx.x, gridDim.x);
+    const bool second = g >= T.t[0].ntiles;
+    const PartTable<K> tb = pick(T, second);
+    const int64_t tile = second ? g - T.t[0].ntiles : g;
     const int64_t row0 = tile * (int64_t)(kBlock * R);
     K k[R];
 #pragma unroll
     for (int c = 0; c < R; ++c) {
         const int64_t r = row0 + (int64_t)c * kBlock + tid;
-        k[c] = r < n ? __builtin_nontemporal_load(keys + r) : K(0);
+        k[c] = r < tb.n ? __builtin_nontemporal_load(tb.keys + r) : K(0);
     }
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < R; ++c) {
         const int64_t r = row0 + (int64_t)c * kBlock + tid;
-        if (r < n)
+        if (r < tb.n)
             atomicAdd(&hist[dest_of(fmix64(key_bits(k[c])), d)], 1u);
     }
     __syncthreads();
     for (int p = tid; p < P; p += kBlock)
-        cnt[(int64_t)p * ntiles + tile] = hist[p];
+        tb.cnt[(int64_t)p * tb.ntiles + tile] = hist[p];
 }
 
 // Block p: exclusive prefix of cnt[p][0..ntiles) in place, total to totals[p].
@@ -65,13 +110,19 @@ __device__ __forceinline__ int scan_slot(int e)
     return e + e / kScanV;
 }
 
-__global__ __launch_bounds__(kBlock) void part_scan_tiles(int64_t *__restrict__ cnt, int64_t ntiles,
-                                                          int64_t *__restrict__ totals)
+// Block b: destination b mod D of table b / D.
+__global__ __launch_bounds__(kBlock) void part_scan_tiles(int64_t *cnt0, int64_t ntiles0,
+                                                          int64_t *totals0, int64_t *cnt1,
+                                                          int64_t ntiles1, int64_t *totals1, int D)
 {
     __shared__ int64_t scratch[kWavesPerBlock];
     __shared__ int64_t buf[kScanChunk + kBlock];
     const int tid = threadIdx.x;
-    int64_t *row = cnt + (int64_t)blockIdx.x * ntiles;
+    const bool second = (int)blockIdx.x >= D;
+    const int p = second ? (int)blockIdx.x - D : (int)blockIdx.x;
+    const int64_t ntiles = second ? ntiles1 : ntiles0;
+    int64_t *totals = second ? totals1 : totals0;
+    int64_t *row = (second ? cnt1 : cnt0) + (int64_t)p * ntiles;
     int64_t carry = 0;
     for (int64_t base = 0; base < ntiles; base += kScanChunk) {
         const int m = (int)(ntiles - base < kScanChunk ? ntiles - base : kScanChunk);
@@ -105,13 +156,16 @@ __global__ __launch_bounds__(kBlock) void part_scan_tiles(int64_t *__restrict__ 
         __syncthreads();  // buf is refilled by the next round
     }
     if (tid == 0)
-        totals[blockIdx.x] = carry;
+        totals[p] = carry;
 }
 
-__global__ __launch_bounds__(kBlock) void part_offsets(const int64_t *__restrict__ totals, int P,
-                                                       int64_t *__restrict__ off)
+// Block t: table t's destination offsets.
+__global__ __launch_bounds__(kBlock) void part_offsets(const int64_t *totals0, int64_t *off0,
+                                                       const int64_t *totals1, int64_t *off1, int P)
 {
     __shared__ int64_t scratch[kWavesPerBlock];
+    const int64_t *totals = blockIdx.x ? totals1 : totals0;
+    int64_t *off = blockIdx.x ? off1 : off0;
     int64_t carry = 0;
     for (int base = 0; base < P; base += kBlock) {
         const int p = base + threadIdx.x;
@@ -290,19 +344,18 @@ __device__ __forceinline__ void scatter_tile(const K *__restrict__ keys,
 }
 
 template <typename K, int R>
-__global__ __launch_bounds__(kBlock) void part_scatter(
-    const K *__restrict__ keys, const int64_t *__restrict__ pay, int64_t n, Dest d,
-    const int64_t *__restrict__ off, const int64_t *__restrict__ pre, int64_t ntiles,
-    K *__restrict__ keys_out, int64_t *__restrict__ pay_out, uint8_t *__restrict__ dig_out,
-    int dshift, int dbits)
+__global__ __launch_bounds__(kBlock) void part_scatter(PartPair<K> T, Dest d, int dshift, int dbits)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int64_t tile = tile_of_block(blockIdx.x, gridDim.x);
+    const int64_t g = tile_of_block(blockIdx.x, gridDim.x);
+    const bool second = g >= T.t[0].ntiles;
+    const PartTable<K> tb = pick(T, second);
+    const int64_t tile = second ? g - T.t[0].ntiles : g;
     scatter_tile<K, R>(
-        keys, pay, tile * (int64_t)(kBlock * R), n, d.ndest, d.nbits,
+        tb.keys, tb.pay, tile * (int64_t)(kBlock * R), tb.n, d.ndest, d.nbits,
         [&](uint64_t h) { return dest_of(h, d); },
-        [&](int p) { return off[p] + pre[(int64_t)p * ntiles + tile]; }, keys_out, pay_out, smem,
-        dig_out, dshift, dbits);
+        [&](int p) { return tb.off[p] + tb.cnt[(int64_t)p * tb.ntiles + tile]; }, tb.keys_out,
+        tb.pay_out, smem, tb.dig, dshift, dbits);
 }
 
 // ---- segmented partition -------------------------------------------------------
@@ -312,166 +365,223 @@ __global__ __launch_bounds__(kBlock) void part_scatter(
 //                   + (rows of (a, q) in earlier tiles of the chunk)
 //                   + (rank inside the tile),
 // i.e. the stable counting-sort position inside segment a.
+template <typename K>
+struct SegTable {
+    const K *keys;
+    const int64_t *pay;
+    const uint8_t *dig;      // digit byte per row
+    const int64_t *segoff;   // [nseg + 1]
+    int64_t *tile_start;     // [nseg + 1]
+    int64_t *chunk_start;    // [nseg + 1]
+    uint32_t *cnt;           // [max_tiles][D]
+    int64_t *csum;           // [max_chunks][D]
+    int64_t *outoff;         // [nseg D + 1]
+    K *keys_out;
+    int64_t *pay_out;
+    int64_t max_tiles, max_chunks;
+};
 
-__global__ __launch_bounds__(kBlock) void seg_plan(const int64_t *__restrict__ segoff, int nseg,
-                                                   int64_t *__restrict__ tile_start,
-                                                   int64_t *__restrict__ chunk_start)
+template <typename K>
+struct SegPair {
+    SegTable<K> t[2];
+};
+
+template <typename K>
+__device__ __forceinline__ SegTable<K> pick(const SegPair<K> &T, bool second)
+{
+    const SegTable<K> &a = T.t[0], &b = T.t[1];
+    SegTable<K> r;
+    r.keys = second ? b.keys : a.keys;
+    r.pay = second ? b.pay : a.pay;
+    r.dig = second ? b.dig : a.dig;
+    r.segoff = second ? b.segoff : a.segoff;
+    r.tile_start = second ? b.tile_start : a.tile_start;
+    r.chunk_start = second ? b.chunk_start : a.chunk_start;
+    r.cnt = second ? b.cnt : a.cnt;
+    r.csum = second ? b.csum : a.csum;
+    r.outoff = second ? b.outoff : a.outoff;
+    r.keys_out = second ? b.keys_out : a.keys_out;
+    r.pay_out = second ? b.pay_out : a.pay_out;
+    r.max_tiles = second ? b.max_tiles : a.max_tiles;
+    r.max_chunks = second ? b.max_chunks : a.max_chunks;
+    return r;
+}
+
+// Block t: tile and chunk starts of every segment of table t.
+template <typename K>
+__global__ __launch_bounds__(kBlock) void seg_plan(SegPair<K> T, int nseg)
 {
     __shared__ int64_t scratch[kWavesPerBlock];
+    const SegTable<K> tb = pick(T, blockIdx.x != 0);
     int64_t tcarry = 0, ccarry = 0;
     for (int base = 0; base < nseg; base += kBlock) {
         const int a = base + threadIdx.x;
         int64_t nt = 0;
         if (a < nseg)
-            nt = (segoff[a + 1] - segoff[a] + kSegTile - 1) / kSegTile;
+            nt = (tb.segoff[a + 1] - tb.segoff[a] + kSegTile - 1) / kSegTile;
         const int64_t nc = (nt + kSegChunkTiles - 1) / kSegChunkTiles;
         int64_t tt, ct;
         const int64_t te = block_excl_scan(nt, scratch, &tt);
         const int64_t ce = block_excl_scan(nc, scratch, &ct);
         if (a < nseg) {
-            tile_start[a] = tcarry + te;
-            chunk_start[a] = ccarry + ce;
+            tb.tile_start[a] = tcarry + te;
+            tb.chunk_start[a] = ccarry + ce;
         }
         tcarry += tt;
         ccarry += ct;
     }
     if (threadIdx.x == 0) {
-        tile_start[nseg] = tcarry;
-        chunk_start[nseg] = ccarry;
+        tb.tile_start[nseg] = tcarry;
+        tb.chunk_start[nseg] = ccarry;
     }
 }
 
-// Block = chunk: per-tile digit counts, stored as the exclusive prefix over
-// the chunk's earlier tiles; chunk totals to csum.  The digits are the bytes
-// the first pass wrote beside its output rows, so this pass reads one byte
-// per row instead of the key.  All of the chunk's bytes are loaded at once,
-// then counted into one LDS histogram per tile.
-__global__ __launch_bounds__(kBlock) void seg_hist(
-    const uint8_t *__restrict__ dig, const int64_t *__restrict__ segoff, int nseg,
-    const int64_t *__restrict__ tile_start, const int64_t *__restrict__ chunk_start, int bits,
-    uint32_t *__restrict__ cnt, int64_t *__restrict__ csum)
+// Block = chunk (the first table's max_chunks blocks, then the second's):
+// per-tile digit counts, stored as the exclusive prefix over the chunk's
+// earlier tiles; chunk totals to csum.  The digits are the bytes the first
+// pass wrote beside its output rows, so this pass reads one byte per row
+// instead of the key.  All of the chunk's bytes are loaded at once, then
+// counted into one LDS histogram per tile.
+template <typename K>
+__global__ __launch_bounds__(kBlock) void seg_hist(SegPair<K> T, int nseg, int bits)
 {
     __shared__ uint32_t hist[kSegChunkTiles][kSegMaxDest];
     constexpr uint32_t kNone = 0xffffffffu;
-    const int64_t c = blockIdx.x;
-    if (c >= chunk_start[nseg])
+    const bool second = (int64_t)blockIdx.x >= T.t[0].max_chunks;
+    const SegTable<K> tb = pick(T, second);
+    const int64_t c = second ? (int64_t)blockIdx.x - T.t[0].max_chunks : (int64_t)blockIdx.x;
+    if (c >= tb.chunk_start[nseg])
         return;
     const int D = 1 << bits, tid = threadIdx.x;
-    const int a = upper_index(chunk_start, 0, nseg, c);
-    const int64_t s1 = segoff[a + 1];
-    const int64_t t0 = tile_start[a] + (c - chunk_start[a]) * kSegChunkTiles;
-    const int nt = (int)(t0 + kSegChunkTiles < tile_start[a + 1] ? kSegChunkTiles
-                                                                  : tile_start[a + 1] - t0);
-    const int64_t r0 = segoff[a] + (t0 - tile_start[a]) * kSegTile;  // chunk's first row
+    const int a = upper_index(tb.chunk_start, 0, nseg, c);
+    const int64_t s1 = tb.segoff[a + 1];
+    const int64_t t0 = tb.tile_start[a] + (c - tb.chunk_start[a]) * kSegChunkTiles;
+    const int nt = (int)(t0 + kSegChunkTiles < tb.tile_start[a + 1] ? kSegChunkTiles
+                                                                    : tb.tile_start[a + 1] - t0);
+    const int64_t r0 = tb.segoff[a] + (t0 - tb.tile_start[a]) * kSegTile;  // chunk's first row
     for (int i = tid; i < kSegChunkTiles * kSegMaxDest; i += kBlock)
         (&hist[0][0])[i] = 0;
-    uint32_t d[kSegChunkTiles * kSegRows];
+    uint32_t dg[kSegChunkTiles * kSegRows];
 #pragma unroll
     for (int j = 0; j < kSegChunkTiles * kSegRows; ++j) {
         const int64_t r = r0 + (int64_t)j * kBlock + tid;  // tile j / kSegRows
-        d[j] = r < s1 ? (uint32_t)__builtin_nontemporal_load(dig + r) : kNone;
+        dg[j] = r < s1 ? (uint32_t)__builtin_nontemporal_load(tb.dig + r) : kNone;
     }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kSegChunkTiles * kSegRows; ++j)
-        if (d[j] != kNone)
-            atomicAdd(&hist[j / kSegRows][d[j]], 1u);
+        if (dg[j] != kNone)
+            atomicAdd(&hist[j / kSegRows][dg[j]], 1u);
     __syncthreads();
     for (int q = tid; q < D; q += kBlock) {
         uint32_t run = 0;
         for (int t = 0; t < nt; ++t) {
-            cnt[(t0 + t) * D + q] = run;
+            tb.cnt[(t0 + t) * D + q] = run;
             run += hist[t][q];
         }
-        csum[c * D + q] = run;
+        tb.csum[c * D + q] = run;
     }
 }
 
-// Block = segment: chunk totals -> exclusive prefix over the segment's chunks
-// (in place); destination bases outoff[a D + q].
-__global__ __launch_bounds__(kBlock) void seg_scan(const int64_t *__restrict__ segoff, int nseg,
-                                                   const int64_t *__restrict__ chunk_start,
-                                                   int bits, int64_t *__restrict__ csum,
-                                                   int64_t *__restrict__ outoff)
+// Block = segment (nseg blocks per table): chunk totals -> exclusive prefix
+// over the segment's chunks (in place); destination bases outoff[a D + q].
+template <typename K>
+__global__ __launch_bounds__(kBlock) void seg_scan(SegPair<K> T, int nseg, int bits)
 {
     __shared__ int64_t scratch[kWavesPerBlock];
     __shared__ int64_t tot[kSegMaxDest];
-    const int a = blockIdx.x, D = 1 << bits, tid = threadIdx.x;
-    const int64_t c0 = chunk_start[a], c1 = chunk_start[a + 1];
+    const bool second = (int)blockIdx.x >= nseg;
+    const SegTable<K> tb = pick(T, second);
+    const int a = second ? (int)blockIdx.x - nseg : (int)blockIdx.x;
+    const int D = 1 << bits, tid = threadIdx.x;
+    const int64_t c0 = tb.chunk_start[a], c1 = tb.chunk_start[a + 1];
     for (int q = tid; q < D; q += kBlock) {
         int64_t run = 0;
         for (int64_t c = c0; c < c1; ++c) {
-            const int64_t v = csum[c * D + q];
-            csum[c * D + q] = run;
+            const int64_t v = tb.csum[c * D + q];
+            tb.csum[c * D + q] = run;
             run += v;
         }
         tot[q] = run;
     }
     __syncthreads();
-    int64_t carry = segoff[a];
+    int64_t carry = tb.segoff[a];
     for (int base = 0; base < D; base += kBlock) {
         const int q = base + tid;
         const int64_t v = q < D ? tot[q] : 0;
         int64_t all;
         const int64_t ex = block_excl_scan(v, scratch, &all);
         if (q < D)
-            outoff[(int64_t)a * D + q] = carry + ex;
+            tb.outoff[(int64_t)a * D + q] = carry + ex;
         carry += all;
     }
     if (a == nseg - 1 && tid == 0)
-        outoff[(int64_t)nseg * D] = segoff[nseg];
+        tb.outoff[(int64_t)nseg * D] = tb.segoff[nseg];
 }
 
+// Block = tile (the first table's max_tiles, then the second's, in
+// XCD-contiguous order over both).
 template <typename K>
-__global__ __launch_bounds__(kBlock) void seg_scatter(
-    const K *__restrict__ keys, const int64_t *__restrict__ pay,
-    const int64_t *__restrict__ segoff, int nseg, const int64_t *__restrict__ tile_start,
-    const int64_t *__restrict__ chunk_start, int shift, int bits,
-    const uint32_t *__restrict__ cnt, const int64_t *__restrict__ csum,
-    const int64_t *__restrict__ outoff, K *__restrict__ keys_out, int64_t *__restrict__ pay_out,
-    const int32_t *gate)
+__global__ __launch_bounds__(kBlock) void seg_scatter(SegPair<K> T, int nseg, int shift, int bits)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    if (gate && *gate == 0)
-        return;
-    const int64_t t = tile_of_block(blockIdx.x, gridDim.x);
-    if (t >= tile_start[nseg])
+    const int64_t g = tile_of_block(blockIdx.x, gridDim.x);
+    const bool second = g >= T.t[0].max_tiles;
+    const SegTable<K> tb = pick(T, second);
+    const int64_t t = second ? g - T.t[0].max_tiles : g;
+    if (t >= tb.tile_start[nseg])
         return;
     const int D = 1 << bits;
-    const int a = upper_index(tile_start, 0, nseg, t);
-    const int64_t lt = t - tile_start[a];
-    const int64_t chunk = chunk_start[a] + lt / kSegChunkTiles;
-    const int64_t r0 = segoff[a] + lt * kSegTile;
-    const int64_t r1 = r0 + kSegTile < segoff[a + 1] ? r0 + kSegTile : segoff[a + 1];
+    const int a = upper_index(tb.tile_start, 0, nseg, t);
+    const int64_t lt = t - tb.tile_start[a];
+    const int64_t chunk = tb.chunk_start[a] + lt / kSegChunkTiles;
+    const int64_t r0 = tb.segoff[a] + lt * kSegTile;
+    const int64_t r1 = r0 + kSegTile < tb.segoff[a + 1] ? r0 + kSegTile : tb.segoff[a + 1];
     scatter_tile<K, kSegRows>(
-        keys, pay, r0, r1, D, bits,
+        tb.keys, tb.pay, r0, r1, D, bits,
         [&](uint64_t h) { return digit_of(h, shift, bits); },
         [&](int q) {
-            return outoff[(int64_t)a * D + q] + csum[chunk * D + q] + (int64_t)cnt[t * D + q];
+            return tb.outoff[(int64_t)a * D + q] + tb.csum[chunk * D + q] +
+                   (int64_t)tb.cnt[t * D + q];
         },
-        keys_out, pay_out, smem);
+        tb.keys_out, tb.pay_out, smem);
 }
 
 template <typename K, int R>
-hipError_t run_partition(const K *keys, const int64_t *pay, int64_t n, int32_t P, int sbits,
-                         K *keys_out, int64_t *pay_out, int64_t *off, uint8_t *dig_out,
-                         int dshift, int dbits, void *ws, hipStream_t s)
+hipError_t run_partition(const PartArgs *tables, int ntables, int32_t P, int sbits, int dshift,
+                         int dbits, hipStream_t s)
 {
     const Dest d = make_dest(P, sbits);
     const int D = d.ndest;
-    const PartLayout L = part_layout(n, D);
-    int64_t *cnt = (int64_t *)((char *)ws + L.cnt_off);
-    int64_t *totals = (int64_t *)((char *)ws + L.totals_off);
-    if (L.ntiles > 0) {
+    PartPair<K> T = {};
+    for (int i = 0; i < ntables; ++i) {
+        const PartArgs &a = tables[i];
+        const PartLayout L = part_layout(a.n, D);
+        PartTable<K> &t = T.t[i];
+        t.keys = (const K *)a.keys;
+        t.pay = a.pay;
+        t.n = a.n;
+        t.ntiles = L.ntiles;
+        t.keys_out = (K *)a.keys_out;
+        t.pay_out = a.pay_out;
+        t.off = a.off;
+        t.dig = a.dig;
+        t.cnt = (int64_t *)((char *)a.ws + L.cnt_off);
+        t.totals = (int64_t *)((char *)a.ws + L.totals_off);
+    }
+    const int64_t tiles = T.t[0].ntiles + T.t[1].ntiles;
+    if (tiles > 0) {
         trace_begin("part_hist", s);
-        hipLaunchKernelGGL((part_hist<K, R>), dim3((unsigned)L.ntiles), dim3(kBlock),
-                           (size_t)D * sizeof(uint32_t), s, keys, n, d, cnt, L.ntiles);
+        hipLaunchKernelGGL((part_hist<K, R>), dim3((unsigned)tiles), dim3(kBlock),
+                           (size_t)D * sizeof(uint32_t), s, T, d);
         trace_end("part_hist", s);
     }
-    hipLaunchKernelGGL(part_scan_tiles, dim3((unsigned)D), dim3(kBlock), 0, s, cnt, L.ntiles,
-                       totals);
-    hipLaunchKernelGGL(part_offsets, dim3(1), dim3(kBlock), 0, s, totals, D, off);
-    if (L.ntiles > 0) {
+    hipLaunchKernelGGL(part_scan_tiles, dim3((unsigned)(D * ntables)), dim3(kBlock), 0, s,
+                       T.t[0].cnt, T.t[0].ntiles, T.t[0].totals, T.t[1].cnt, T.t[1].ntiles,
+                       T.t[1].totals, D);
+    hipLaunchKernelGGL(part_offsets, dim3((unsigned)ntables), dim3(kBlock), 0, s, T.t[0].totals,
+                       T.t[0].off, T.t[1].totals, T.t[1].off, D);
+    if (tiles > 0) {
         const size_t lds = scatter_lds(kBlock * R, D, (int)sizeof(K)).total;
         if (lds > kMaxLdsBytes)
             return hipErrorInvalidValue;  // cannot happen for D <= MDX_MAX_P
@@ -480,82 +590,86 @@ hipError_t run_partition(const K *keys, const int64_t *pay, int64_t n, int32_t P
         if (e != hipSuccess)
             return e;
         trace_begin("part_scatter", s);
-        hipLaunchKernelGGL((part_scatter<K, R>), dim3((unsigned)L.ntiles), dim3(kBlock), lds, s,
-                           keys, pay, n, d, off, cnt, L.ntiles, keys_out, pay_out, dig_out,
-                           dshift, dbits);
+        hipLaunchKernelGGL((part_scatter<K, R>), dim3((unsigned)tiles), dim3(kBlock), lds, s, T,
+                           d, dshift, dbits);
         trace_end("part_scatter", s);
     }
     return hipGetLastError();
 }
 
-}  // namespace
-
-hipError_t launch_partition(const void *keys, const int64_t *pay, int64_t n, int key_bytes,
-                            int32_t P, int sbits, void *keys_out, int64_t *pay_out, int64_t *off,
-                            uint8_t *dig_out, int dshift, int dbits, void *ws, hipStream_t s)
+template <typename K>
+hipError_t run_seg_partition(const SegArgs *tables, int ntables, int64_t nseg, int shift,
+                             int bits, hipStream_t s)
 {
-    const int R = part_rows_per_thread(P << sbits);
-    if (key_bytes == 8) {
-        if (R == kPartRowsSmall)
-            return run_partition<int64_t, kPartRowsSmall>((const int64_t *)keys, pay, n, P, sbits,
-                                                          (int64_t *)keys_out, pay_out, off,
-                                                          dig_out, dshift, dbits, ws, s);
-        return run_partition<int64_t, kPartRowsLarge>((const int64_t *)keys, pay, n, P, sbits,
-                                                      (int64_t *)keys_out, pay_out, off, dig_out,
-                                                      dshift, dbits, ws, s);
+    SegPair<K> T = {};
+    for (int i = 0; i < ntables; ++i) {
+        const SegArgs &a = tables[i];
+        const SegLayout L = seg_layout(a.n, nseg, bits);
+        char *b = (char *)a.ws;
+        SegTable<K> &t = T.t[i];
+        t.keys = (const K *)a.keys;
+        t.pay = a.pay;
+        t.dig = a.dig;
+        t.segoff = a.segoff;
+        t.tile_start = (int64_t *)(b + L.tile_start_off);
+        t.chunk_start = (int64_t *)(b + L.chunk_start_off);
+        t.cnt = (uint32_t *)(b + L.cnt_off);
+        t.csum = (int64_t *)(b + L.csum_off);
+        t.outoff = a.outoff;
+        t.keys_out = (K *)a.keys_out;
+        t.pay_out = a.pay_out;
+        t.max_tiles = L.max_tiles;
+        t.max_chunks = L.max_chunks;
     }
-    if (R == kPartRowsSmall)
-        return run_partition<int32_t, kPartRowsSmall>((const int32_t *)keys, pay, n, P, sbits,
-                                                      (int32_t *)keys_out, pay_out, off, dig_out,
-                                                      dshift, dbits, ws, s);
-    return run_partition<int32_t, kPartRowsLarge>((const int32_t *)keys, pay, n, P, sbits,
-                                                  (int32_t *)keys_out, pay_out, off, dig_out,
-                                                  dshift, dbits, ws, s);
-}
-
-hipError_t launch_seg_partition(const void *keys, const int64_t *pay, const uint8_t *dig,
-                                int64_t n, int key_bytes, const int64_t *segoff, int64_t nseg,
-                                int shift, int bits, void *keys_out, int64_t *pay_out,
-                                int64_t *outoff, void *ws, const int32_t *gate, hipStream_t s)
-{
-    const SegLayout L = seg_layout(n, nseg, bits);
-    char *b = (char *)ws;
-    int64_t *tile_start = (int64_t *)(b + L.tile_start_off);
-    int64_t *chunk_start = (int64_t *)(b + L.chunk_start_off);
-    uint32_t *cnt = (uint32_t *)(b + L.cnt_off);
-    int64_t *csum = (int64_t *)(b + L.csum_off);
     const int ns = (int)nseg;
-    hipLaunchKernelGGL(seg_plan, dim3(1), dim3(kBlock), 0, s, segoff, ns, tile_start, chunk_start);
-    const size_t lds = scatter_lds(kSegTile, 1 << bits, key_bytes).total;
+    const size_t lds = scatter_lds(kSegTile, 1 << bits, (int)sizeof(K)).total;
     if (lds > kMaxLdsBytes)
         return hipErrorInvalidValue;  // cannot happen for bits <= 8
+    hipLaunchKernelGGL(seg_plan<K>, dim3((unsigned)ntables), dim3(kBlock), 0, s, T, ns);
     trace_begin("seg_hist", s);
-    hipLaunchKernelGGL(seg_hist, dim3((unsigned)L.max_chunks), dim3(kBlock), 0, s, dig, segoff,
-                       ns, tile_start, chunk_start, bits, cnt, csum);
+    hipLaunchKernelGGL(seg_hist<K>, dim3((unsigned)(T.t[0].max_chunks + T.t[1].max_chunks)),
+                       dim3(kBlock), 0, s, T, ns, bits);
     trace_end("seg_hist", s);
-    hipLaunchKernelGGL(seg_scan, dim3((unsigned)ns), dim3(kBlock), 0, s, segoff, ns, chunk_start,
-                       bits, csum, outoff);
-    hipError_t e;
+    hipLaunchKernelGGL(seg_scan<K>, dim3((unsigned)(ns * ntables)), dim3(kBlock), 0, s, T, ns,
+                       bits);
+    hipError_t e = hipFuncSetAttribute((const void *)seg_scatter<K>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess)
+        return e;
     trace_begin("seg_scatter", s);
-    if (key_bytes == 8) {
-        e = hipFuncSetAttribute((const void *)seg_scatter<int64_t>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess)
-            return e;
-        hipLaunchKernelGGL(seg_scatter<int64_t>, dim3((unsigned)L.max_tiles), dim3(kBlock), lds, s,
-                           (const int64_t *)keys, pay, segoff, ns, tile_start, chunk_start, shift,
-                           bits, cnt, csum, outoff, (int64_t *)keys_out, pay_out, gate);
-    } else {
-        e = hipFuncSetAttribute((const void *)seg_scatter<int32_t>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess)
-            return e;
-        hipLaunchKernelGGL(seg_scatter<int32_t>, dim3((unsigned)L.max_tiles), dim3(kBlock), lds, s,
-                           (const int32_t *)keys, pay, segoff, ns, tile_start, chunk_start, shift,
-                           bits, cnt, csum, outoff, (int32_t *)keys_out, pay_out, gate);
-    }
+    hipLaunchKernelGGL(seg_scatter<K>, dim3((unsigned)(T.t[0].max_tiles + T.t[1].max_tiles)),
+                       dim3(kBlock), lds, s, T, ns, shift, bits);
     trace_end("seg_scatter", s);
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_partition(const PartArgs *tables, int ntables, int key_bytes, int32_t P,
+                            int sbits, int dshift, int dbits, hipStream_t s)
+{
+    if (ntables < 1 || ntables > 2)
+        return hipErrorInvalidValue;
+    const bool small = part_rows_per_thread(P << sbits) == kPartRowsSmall;
+    if (key_bytes == 8)
+        return small ? run_partition<int64_t, kPartRowsSmall>(tables, ntables, P, sbits, dshift,
+                                                              dbits, s)
+                     : run_partition<int64_t, kPartRowsLarge>(tables, ntables, P, sbits, dshift,
+                                                              dbits, s);
+    return small ? run_partition<int32_t, kPartRowsSmall>(tables, ntables, P, sbits, dshift, dbits,
+                                                          s)
+                 : run_partition<int32_t, kPartRowsLarge>(tables, ntables, P, sbits, dshift, dbits,
+                                                          s);
+}
+
+hipError_t launch_seg_partition(const SegArgs *tables, int ntables, int key_bytes, int64_t nseg,
+                                int shift, int bits, hipStream_t s)
+{
+    if (ntables < 1 || ntables > 2)
+        return hipErrorInvalidValue;
+    if (key_bytes == 8)
+        return run_seg_partition<int64_t>(tables, ntables, nseg, shift, bits, s);
+    return run_seg_partition<int32_t>(tables, ntables, nseg, shift, bits, s);
 }
 
 }  // namespace mdx

@@ -58,6 +58,42 @@ def test_merge_repeated_keys_radix(dtype):
     assert_join_equals_oracle(kl, vl, kr, vr, 8, got)
 
 
+@pytest.mark.parametrize("nl,nr,frac,P,dtype", [
+    (3_000, 200_000, 0.5, 2, np.int64),   # a sub-bucket's probe rows span 13 batches
+    (6_000, 8_000, 1.0, 1, np.int64),     # one sub-bucket, every probe row matches
+    (6_000, 8_000, 1.0, 1, np.int32),
+    (6_000, 6_400, 1.0, 1, np.int64),
+])
+def test_merge_join_routes(nl, nr, frac, P, dtype):
+    """Sub-buckets whose probe rows span several batches (looked up again
+    for the output) and sub-buckets with many output rows, against the
+    oracle."""
+    announce(f"merge routes {nl}x{nr} f={frac} P={P} {np.dtype(dtype).name}")
+    kl, vl, kr, vr = match_fraction_tables(nl, nr, frac, seed=nl + nr, key_dtype=dtype)
+    total = oracle.join(kl, vl, kr, vr, materialize=False)["total"]
+    got = run_merge(kl, vl, kr, vr, P, cap=total)
+    assert got["status"] == 0
+    assert_join_equals_oracle(kl, vl, kr, vr, P, got)
+
+
+def test_merge_some_sub_buckets_repeat_keys():
+    """20 build keys appear twice among 300000 distinct ones: only the
+    sub-buckets holding them have probe rows with two matches."""
+    announce("merge mixed routes")
+    rng = np.random.default_rng(12)
+    base = rng.permutation(300_000).astype(np.int64)
+    kl = np.concatenate([base, base[rng.integers(0, base.size, 20)]])
+    kl = kl[rng.permutation(kl.size)]
+    kr = np.concatenate([base[rng.integers(0, base.size, 90_000)],
+                         rng.integers(300_000, 600_000, 210_000)])
+    kr = kr[rng.permutation(kr.size)]
+    vl, vr = np.arange(kl.size, dtype=np.int64), np.arange(kr.size, dtype=np.int64)
+    total = oracle.join(kl, vl, kr, vr, materialize=False)["total"]
+    got = run_merge(kl, vl, kr, vr, 8, cap=total)
+    assert got["status"] == 0
+    assert_join_equals_oracle(kl, vl, kr, vr, 8, got)
+
+
 def test_merge_int32_keys():
     announce("merge int32")
     kl, vl, kr, vr = match_fraction_tables(300_000, 250_000, 0.3, seed=4, key_dtype=np.int32)
