@@ -96,18 +96,25 @@ __device__ bool block_any_dup(const TView &v)
 
 // ---- build -----------------------------------------------------------------
 
-__global__ __launch_bounds__(kBlock) void table_setup(const int64_t *__restrict__ off_in, int64_t n,
-                                                      int64_t *__restrict__ off_tab,
-                                                      int32_t *__restrict__ flags,
-                                                      int64_t *__restrict__ bump, int P)
+// One block: the table's sanitized build offsets, cleared per-partition flags.
+__device__ void table_setup_block(const int64_t *off_in, int64_t n, int64_t *off_tab,
+                                  int32_t *flags, int64_t *bump, int P, int64_t *scratch)
 {
-    __shared__ int64_t scratch[kWavesPerBlock];
     if (off_in)
         sanitize_offsets(off_in, off_tab, P, n, scratch);
     for (int p = threadIdx.x; p < P; p += kBlock) {
         flags[p] = 0;
         bump[p] = 0;
     }
+}
+
+__global__ __launch_bounds__(kBlock) void table_setup(const int64_t *__restrict__ off_in, int64_t n,
+                                                      int64_t *__restrict__ off_tab,
+                                                      int32_t *__restrict__ flags,
+                                                      int64_t *__restrict__ bump, int P)
+{
+    __shared__ int64_t scratch[kWavesPerBlock];
+    table_setup_block(off_in, n, off_tab, flags, bump, P, scratch);
 }
 
 __global__ __launch_bounds__(kBlock) void tbl_init(TView v)
@@ -318,12 +325,11 @@ __global__ __launch_bounds__(kBlock) void grp_scatter(const K *__restrict__ keys
 
 // ---- probe -----------------------------------------------------------------
 
-__global__ __launch_bounds__(kBlock) void probe_plan(const int64_t *__restrict__ offR, int64_t n,
-                                                     int P, ProbeWs w, const int32_t *skip)
+// Block 0 plans the probe tiles; every block clears its share of the
+// chained-scan status.
+__device__ void probe_plan_blocks(const int64_t *offR, int64_t n, int P, const ProbeWs &w,
+                                  int64_t *scratch)
 {
-    if (skipped(skip))
-        return;
-    __shared__ int64_t scratch[kWavesPerBlock];
     if (blockIdx.x == 0) {
         sanitize_offsets(offR, w.off, P, n, scratch);
         int64_t carry = 0;
@@ -347,6 +353,35 @@ __global__ __launch_bounds__(kBlock) void probe_plan(const int64_t *__restrict__
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < w.max_tiles; i += stride)
         w.status[i] = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void probe_plan(const int64_t *__restrict__ offR, int64_t n,
+                                                     int P, ProbeWs w, const int32_t *skip)
+{
+    if (skipped(skip))
+        return;
+    __shared__ int64_t scratch[kWavesPerBlock];
+    probe_plan_blocks(offR, n, P, w, scratch);
+}
+
+// Set-up of a merge's global-table join in one block: per-partition build
+// and probe offsets taken from the first-pass offsets (every stride-th
+// entry), the table's offsets and flags, the probe plan.
+__global__ __launch_bounds__(kBlock) void fallback_setup(
+    const int64_t *__restrict__ offAL, const int64_t *__restrict__ offAR, int stride, int P,
+    int64_t n_build, int64_t n_probe, int64_t *offPL, int64_t *offPR, int64_t *off_tab,
+    int32_t *flags, int64_t *bump, ProbeWs w, const int32_t *skip)
+{
+    if (skipped(skip))
+        return;
+    __shared__ int64_t scratch[kWavesPerBlock];
+    for (int p = threadIdx.x; p <= P; p += kBlock) {
+        offPL[p] = offAL[(int64_t)p * stride];
+        offPR[p] = offAR[(int64_t)p * stride];
+    }
+    __syncthreads();
+    table_setup_block(offPL, n_build, off_tab, flags, bump, P, scratch);
+    probe_plan_blocks(offPR, n_probe, P, w, scratch);
 }
 
 template <typename K>
@@ -596,6 +631,16 @@ hipError_t launch_build(const void *keys, const int64_t *pay, int key_bytes, con
     if (key_bytes == 8)
         return run_build<int64_t>((const int64_t *)keys, pay, v, status, s);
     return run_build<int32_t>((const int32_t *)keys, pay, v, status, s);
+}
+
+hipError_t launch_fallback_setup(const int64_t *offAL, const int64_t *offAR, int stride,
+                                 int32_t P, int64_t n_build, int64_t n_probe, int64_t *offPL,
+                                 int64_t *offPR, int64_t *off_tab, int32_t *flags, int64_t *bump,
+                                 const ProbeWs &w, const int32_t *skip, hipStream_t s)
+{
+    hipLaunchKernelGGL(fallback_setup, dim3(1), dim3(kBlock), 0, s, offAL, offAR, stride, P,
+                       n_build, n_probe, offPL, offPR, off_tab, flags, bump, w, skip);
+    return hipGetLastError();
 }
 
 hipError_t launch_probe_plan(const int64_t *offR, int64_t n, int32_t P, const ProbeWs &w,

@@ -601,34 +601,30 @@ static hipError_t enqueue_merge(const mdx_merge_desc &d, void *d_ws, hipStream_t
     if (e == hipSuccess)
         e = launch_rjoin(lk, lv, subL, rk, rv, subR, key_type, P, pl.qbits, jw, o, d_status,
                          stream);
-    if (e == hipSuccess)
-        e = launch_rjoin_finalize(P, pl.qbits, jw, o, stream);
 
     // 4. otherwise (a sub-bucket too large for LDS: heavy key repetition),
     // the global-table join over the first-pass output; its kernels do
     // nothing when the radix join ran.  No sub-bucket can exceed the table
     // when the whole build side fits it: then they are not launched.
-    if (n_left <= kJoinCap)
+    if (n_left <= kJoinCap) {
+        if (e == hipSuccess)
+            e = launch_merge_finalize(P, pl.qbits, jw, nullptr, o, stream);
         return e;
+    }
     int64_t *offPL = (int64_t *)(b + M.offPL_off), *offPR = (int64_t *)(b + M.offPR_off);
     mdx_table t = carve_table(b + M.table_off, M.tl.bytes, n_left, P, key_type);
     const ProbeWs w = probe_ws(b + M.probe_off, M.ql);
     if (e == hipSuccess)
-        e = launch_gather_offsets(offAL, P, 1 << pl.q1bits, offPL, stream);
-    if (e == hipSuccess)
-        e = launch_gather_offsets(offAR, P, 1 << pl.q1bits, offPR, stream);
-    if (e == hipSuccess)
-        e = launch_table_setup(offPL, n_left, t.d_offsets, t.d_flags, t.d_bump, P, stream);
+        e = launch_fallback_setup(offAL, offAR, 1 << pl.q1bits, P, n_left, n_right, offPL, offPR,
+                                  t.d_offsets, t.d_flags, t.d_bump, w, jw.use, stream);
     TView v = make_view(t, t.d_offsets, 0, P);
     v.skip = jw.use;
     if (e == hipSuccess)
         e = launch_build(lk1, lv1, key_type, v, d_status, stream);
     if (e == hipSuccess)
-        e = launch_probe_plan(offPR, n_right, P, w, jw.use, stream);
-    if (e == hipSuccess)
         e = launch_probe_group(rk1, rv1, key_type, P, v, 0, w, o, d_status, stream);
     if (e == hipSuccess)
-        e = launch_probe_finalize(P, w, o, jw.use, stream);
+        e = launch_merge_finalize(P, pl.qbits, jw, &w, o, stream);
     return e;
 }
 

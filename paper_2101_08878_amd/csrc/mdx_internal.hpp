@@ -350,6 +350,15 @@ hipError_t launch_build(const void *keys, const int64_t *pay, int key_bytes, con
 hipError_t launch_table_setup(const int64_t *off_in, int64_t n, int64_t *off_tab, int32_t *flags,
                               int64_t *bump, int32_t P, hipStream_t s);
 
+// A merge's global-table join set-up, in one launch (nothing when *skip):
+// offPL / offPR[p] = offAL / offAR[p stride] (per-partition offsets from the
+// first pass's), then launch_table_setup(offPL, n_build, ...) and
+// launch_probe_plan(offPR, n_probe, ...).
+hipError_t launch_fallback_setup(const int64_t *offAL, const int64_t *offAR, int stride,
+                                 int32_t P, int64_t n_build, int64_t n_probe, int64_t *offPL,
+                                 int64_t *offPR, int64_t *off_tab, int32_t *flags, int64_t *bump,
+                                 const ProbeWs &w, const int32_t *skip, hipStream_t s);
+
 // Probe: plan tiles from the probe offsets (sanitized for n probe rows, once
 // per probe), probe one view (group g), finalize the output offsets.
 hipError_t launch_probe_plan(const int64_t *offR, int64_t n, int32_t P, const ProbeWs &w,
@@ -368,12 +377,11 @@ hipError_t launch_rjoin(const void *lk, const int64_t *lv, const int64_t *subL, 
                         const int64_t *rv, const int64_t *subR, int key_bytes, int32_t P,
                         int qbits, const RJoinWs &w, const ProbeOut &o, int32_t *status,
                         hipStream_t s);
-hipError_t launch_rjoin_finalize(int32_t P, int qbits, const RJoinWs &w, const ProbeOut &o,
-                                 hipStream_t s);
+// A merge's output offsets: the radix join's when it ran, else (pw non-null)
+// the global-table probe's.
+hipError_t launch_merge_finalize(int32_t P, int qbits, const RJoinWs &w, const ProbeWs *pw,
+                                 const ProbeOut &o, hipStream_t s);
 
-// Copy every `stride`-th entry of a[0..P*stride] into out[0..P].
-hipError_t launch_gather_offsets(const int64_t *a, int32_t P, int stride, int64_t *out,
-                                 hipStream_t s);
 
 // ---- transpose sum (y = x + x^T, float64) -------------------------------------------
 hipError_t launch_transpose_sum(const double *x, double *y, int64_t n, hipStream_t s);

@@ -357,21 +357,24 @@ __attribute__((amdgpu_waves_per_eu(kJoinSimdWaves, kJoinSimdWaves))) void rj_joi
     }
 }
 
-__global__ __launch_bounds__(kBlock) void rj_finalize(int P, int qbits, RJoinWs w, ProbeOut o)
+// Output offsets of a merge: from the radix join's chained scan when it ran
+// (*w.use), else from the global-table probe's (probe tiles, partition-major).
+__global__ __launch_bounds__(kBlock) void merge_finalize(int P, int qbits, RJoinWs w, ProbeWs pw,
+                                                         bool fallback, ProbeOut o)
 {
-    if (*w.use == 0)
-        return;
-    const int64_t S = w.S;
-    const int64_t total = (int64_t)(ld_agent(w.status + S - 1) & kValMask);
-    for (int p = threadIdx.x; p <= P; p += kBlock)
-        o.offsets[p] = p < P ? w.tile_base[(int64_t)p << qbits] : total;
-}
-
-__global__ __launch_bounds__(kBlock) void gather_offsets(const int64_t *__restrict__ a, int P,
-                                                         int stride, int64_t *__restrict__ out)
-{
-    for (int p = threadIdx.x; p <= P; p += kBlock)
-        out[p] = a[(int64_t)p * stride];
+    if (*w.use != 0) {
+        const int64_t S = w.S;
+        const int64_t total = (int64_t)(ld_agent(w.status + S - 1) & kValMask);
+        for (int p = threadIdx.x; p <= P; p += kBlock)
+            o.offsets[p] = p < P ? w.tile_base[(int64_t)p << qbits] : total;
+    } else if (fallback) {
+        const int64_t TT = pw.tile_start[P];
+        const int64_t total = TT > 0 ? (int64_t)(ld_agent(pw.status + TT - 1) & kValMask) : 0;
+        for (int p = threadIdx.x; p <= P; p += kBlock) {
+            const int64_t t = pw.tile_start[p];
+            o.offsets[p] = t < TT ? pw.tile_base[t] : total;
+        }
+    }
 }
 
 }  // namespace
@@ -408,17 +411,12 @@ hipError_t launch_rjoin(const void *lk, const int64_t *lv, const int64_t *subL, 
     return hipGetLastError();
 }
 
-hipError_t launch_rjoin_finalize(int32_t P, int qbits, const RJoinWs &w, const ProbeOut &o,
-                                 hipStream_t s)
+hipError_t launch_merge_finalize(int32_t P, int qbits, const RJoinWs &w, const ProbeWs *pw,
+                                 const ProbeOut &o, hipStream_t s)
 {
-    hipLaunchKernelGGL(rj_finalize, dim3(1), dim3(kBlock), 0, s, P, qbits, w, o);
-    return hipGetLastError();
-}
-
-hipError_t launch_gather_offsets(const int64_t *a, int32_t P, int stride, int64_t *out,
-                                 hipStream_t s)
-{
-    hipLaunchKernelGGL(gather_offsets, dim3(1), dim3(kBlock), 0, s, a, P, stride, out);
+    const ProbeWs none = {};
+    hipLaunchKernelGGL(merge_finalize, dim3(1), dim3(kBlock), 0, s, P, qbits, w, pw ? *pw : none,
+                       pw != nullptr, o);
     return hipGetLastError();
 }
 
