@@ -582,11 +582,19 @@ __global__ __launch_bounds__(kBlock) void probe_finalize(int P, ProbeWs w, Probe
     }
 }
 
+// Workgroups of the grid-stride build and probe kernels: a full device, or
+// fewer when the caller sizes the grid to its rows (max_blocks > 0).
+static int table_grid(int max_blocks)
+{
+    const int full = device_fill_blocks();
+    return max_blocks > 0 && max_blocks < full ? max_blocks : full;
+}
+
 template <typename K>
 hipError_t run_build(const K *keys, const int64_t *pay, const TView &v, int32_t *status,
-                     hipStream_t s)
+                     int max_blocks, hipStream_t s)
 {
-    const int G = device_fill_blocks();
+    const int G = table_grid(max_blocks);
     trace_begin("tbl_init", s);
     hipLaunchKernelGGL(tbl_init, dim3(G), dim3(kBlock), 0, s, v);
     trace_end("tbl_init", s);
@@ -602,9 +610,10 @@ hipError_t run_build(const K *keys, const int64_t *pay, const TView &v, int32_t 
 
 template <typename K>
 hipError_t run_probe_group(const K *pk, const int64_t *pv, const TView &v, int group,
-                           const ProbeWs &w, const ProbeOut &o, int32_t *status, hipStream_t s)
+                           const ProbeWs &w, const ProbeOut &o, int32_t *status, int max_blocks,
+                           hipStream_t s)
 {
-    const int G = device_fill_blocks();
+    const int G = table_grid(max_blocks);
     trace_begin("probe_chain", s);
     hipLaunchKernelGGL((probe_chain<K>), dim3(G), dim3(kBlock), 0, s, pk, pv, v, group, w, o,
                        status);
@@ -626,11 +635,11 @@ hipError_t launch_table_setup(const int64_t *off_in, int64_t n, int64_t *off_tab
 }
 
 hipError_t launch_build(const void *keys, const int64_t *pay, int key_bytes, const TView &v,
-                        int32_t *status, hipStream_t s)
+                        int32_t *status, int max_blocks, hipStream_t s)
 {
     if (key_bytes == 8)
-        return run_build<int64_t>((const int64_t *)keys, pay, v, status, s);
-    return run_build<int32_t>((const int32_t *)keys, pay, v, status, s);
+        return run_build<int64_t>((const int64_t *)keys, pay, v, status, max_blocks, s);
+    return run_build<int32_t>((const int32_t *)keys, pay, v, status, max_blocks, s);
 }
 
 hipError_t launch_fallback_setup(const int64_t *offAL, const int64_t *offAR, int stride,
@@ -653,12 +662,14 @@ hipError_t launch_probe_plan(const int64_t *offR, int64_t n, int32_t P, const Pr
 
 hipError_t launch_probe_group(const void *pkeys, const int64_t *ppay, int key_bytes, int32_t P,
                               const TView &v, int group, const ProbeWs &w, const ProbeOut &o,
-                              int32_t *status, hipStream_t s)
+                              int32_t *status, int max_blocks, hipStream_t s)
 {
     (void)P;
     if (key_bytes == 8)
-        return run_probe_group<int64_t>((const int64_t *)pkeys, ppay, v, group, w, o, status, s);
-    return run_probe_group<int32_t>((const int32_t *)pkeys, ppay, v, group, w, o, status, s);
+        return run_probe_group<int64_t>((const int64_t *)pkeys, ppay, v, group, w, o, status,
+                                        max_blocks, s);
+    return run_probe_group<int32_t>((const int32_t *)pkeys, ppay, v, group, w, o, status,
+                                    max_blocks, s);
 }
 
 hipError_t launch_probe_finalize(int32_t P, const ProbeWs &w, const ProbeOut &o,

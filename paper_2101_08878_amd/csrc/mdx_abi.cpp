@@ -314,7 +314,8 @@ int32_t mdx_join_build(const void *d_keys, const int64_t *d_payload, const int64
     hipError_t e = launch_table_setup(d_offsets, n, t.d_offsets, t.d_flags, t.d_bump, P, stream);
     if (e != hipSuccess)
         return hip_fail(e, W);
-    e = launch_build(d_keys, d_payload, key_type, make_view(t, t.d_offsets, 0, P), d_status, stream);
+    e = launch_build(d_keys, d_payload, key_type, make_view(t, t.d_offsets, 0, P), d_status, 0,
+                     stream);
     if (e != hipSuccess)
         return hip_fail(e, W);
     *h_table = t;
@@ -393,7 +394,7 @@ int32_t mdx_join_probe(const mdx_table *h_table, const void *d_keys, const int64
     hipError_t e = launch_probe_plan(d_offsets, n, P, w, nullptr, stream);
     if (e == hipSuccess)
         e = launch_probe_group(d_keys, d_payload, kt, P, make_view(t, t.d_offsets, 0, P), 0, w, o,
-                               d_status, stream);
+                               d_status, 0, stream);
     if (e == hipSuccess)
         e = launch_probe_finalize(P, w, o, nullptr, stream);
     return e == hipSuccess ? MDX_OK : hip_fail(e, W);
@@ -619,10 +620,14 @@ static hipError_t enqueue_merge(const mdx_merge_desc &d, void *d_ws, hipStream_t
                                   t.d_offsets, t.d_flags, t.d_bump, w, jw.use, stream);
     TView v = make_view(t, t.d_offsets, 0, P);
     v.skip = jw.use;
+    // grids sized to the rows (~16K per workgroup): these launches mostly
+    // return at once, and return sooner with fewer workgroups
+    auto blocks = [](int64_t rows) { return (int)std::min<int64_t>((rows >> 14) + 1, 1 << 20); };
     if (e == hipSuccess)
-        e = launch_build(lk1, lv1, key_type, v, d_status, stream);
+        e = launch_build(lk1, lv1, key_type, v, d_status, blocks(n_left), stream);
     if (e == hipSuccess)
-        e = launch_probe_group(rk1, rv1, key_type, P, v, 0, w, o, d_status, stream);
+        e = launch_probe_group(rk1, rv1, key_type, P, v, 0, w, o, d_status, blocks(n_right),
+                               stream);
     if (e == hipSuccess)
         e = launch_merge_finalize(P, pl.qbits, jw, &w, o, stream);
     return e;

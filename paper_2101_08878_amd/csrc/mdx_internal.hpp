@@ -341,9 +341,11 @@ int device_fill_blocks();
 void trace_begin(const char *kernel, hipStream_t s);
 void trace_end(const char *kernel, hipStream_t s);
 
-// Build a view: init slots, insert rows, group repeated keys.
+// Build a view: init slots, insert rows, group repeated keys.  The
+// grid-stride kernels of build and probe run on a full device, or on
+// max_blocks workgroups when 0 < max_blocks < that.
 hipError_t launch_build(const void *keys, const int64_t *pay, int key_bytes, const TView &v,
-                        int32_t *status, hipStream_t s);
+                        int32_t *status, int max_blocks, hipStream_t s);
 
 // Copy the build offsets (sanitized, for n build rows) into the table and
 // clear per-partition flags.  off_in may be null (flags only).
@@ -365,7 +367,7 @@ hipError_t launch_probe_plan(const int64_t *offR, int64_t n, int32_t P, const Pr
                              const int32_t *skip, hipStream_t s);
 hipError_t launch_probe_group(const void *pkeys, const int64_t *ppay, int key_bytes, int32_t P,
                               const TView &v, int group, const ProbeWs &w, const ProbeOut &o,
-                              int32_t *status, hipStream_t s);
+                              int32_t *status, int max_blocks, hipStream_t s);
 hipError_t launch_probe_finalize(int32_t P, const ProbeWs &w, const ProbeOut &o,
                                  const int32_t *skip, hipStream_t s);
 
