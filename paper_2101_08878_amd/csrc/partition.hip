@@ -79,18 +79,50 @@ __global__ __launch_bounds__(kBlock) void part_hist(PartPair<K> T, Dest d)
     const PartTable<K> tb = pick(T, second);
     const int64_t tile = second ? g - T.t[0].ntiles : g;
     const int64_t row0 = tile * (int64_t)(kBlock * R);
-    K k[R];
+    // Keys are read 16 bytes per lane when the column is 16-byte aligned
+    // (the counts do not depend on which thread reads which row).
+    constexpr int V = 16 / (int)sizeof(K);  // keys per 16-byte load
+    if (R % V == 0 && ((uintptr_t)tb.keys & 15) == 0) {
+        // Thread tid, load j: rows row0 + (j kBlock + tid) V + [0, V).
+        typedef K KV __attribute__((ext_vector_type(V)));
+        K k[R];
 #pragma unroll
-    for (int c = 0; c < R; ++c) {
-        const int64_t r = row0 + (int64_t)c * kBlock + tid;
-        k[c] = r < tb.n ? __builtin_nontemporal_load(tb.keys + r) : K(0);
-    }
-    __syncthreads();
+        for (int j = 0; j < R / V; ++j) {
+            const int64_t r = row0 + ((int64_t)j * kBlock + tid) * V;
+            if (r + V <= tb.n) {
+                const KV x = __builtin_nontemporal_load((const KV *)(tb.keys + r));
 #pragma unroll
-    for (int c = 0; c < R; ++c) {
-        const int64_t r = row0 + (int64_t)c * kBlock + tid;
-        if (r < tb.n)
-            atomicAdd(&hist[dest_of(fmix64(key_bits(k[c])), d)], 1u);
+                for (int v = 0; v < V; ++v)
+                    k[j * V + v] = x[v];
+            } else {
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+                    k[j * V + v] = r + v < tb.n ? tb.keys[r + v] : K(0);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < R / V; ++j) {
+            const int64_t r = row0 + ((int64_t)j * kBlock + tid) * V;
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+                if (r + v < tb.n)
+                    atomicAdd(&hist[dest_of(fmix64(key_bits(k[j * V + v])), d)], 1u);
+        }
+    } else {
+        K k[R];
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            const int64_t r = row0 + (int64_t)c * kBlock + tid;
+            k[c] = r < tb.n ? __builtin_nontemporal_load(tb.keys + r) : K(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            const int64_t r = row0 + (int64_t)c * kBlock + tid;
+            if (r < tb.n)
+                atomicAdd(&hist[dest_of(fmix64(key_bits(k[c])), d)], 1u);
+        }
     }
     __syncthreads();
     for (int p = tid; p < P; p += kBlock)

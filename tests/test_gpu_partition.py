@@ -92,3 +92,34 @@ def test_partition_paper_scale_bit_exact(golden_dir):
     want = oracle.hash_partition(kr, vr, 32)
     for g, w in zip(got, want):
         assert np.array_equal(g, w)
+
+
+@pytest.mark.parametrize("dtype", [np.int64, np.int32])
+@pytest.mark.parametrize("shift", [1, 2, 3])
+def test_partition_key_column_not_16_byte_aligned(dtype, shift):
+    """A key column that starts 4, 8 or 12 bytes past a 16-byte boundary (a
+    slice of a larger column): the histogram cannot read it 16 bytes per
+    lane and must take the per-row path, with the same result."""
+    import torch
+
+    import paper_2101_08878_amd as mdx
+    from tests.gpu_util import host
+
+    itemsize = np.dtype(dtype).itemsize
+    if (shift * 4) % itemsize:
+        pytest.skip("offset not a multiple of the key width")
+    skip = shift * 4 // itemsize
+    announce(f"partition unaligned keys {np.dtype(dtype).name} +{shift * 4} B")
+    n = N_RAGGED
+    keys = np.random.default_rng(40 + shift).integers(-10**6, 10**6, n + skip).astype(dtype)
+    pay = np.arange(n, dtype=np.int64)
+    base = torch.from_numpy(keys).to("cuda")
+    assert base.data_ptr() % 16 == 0
+    kd = base[skip:]
+    assert kd.data_ptr() % 16 != 0
+    for P in [7, 32]:
+        ko, vo, off = mdx.mdx_hash_partition(kd, torch.from_numpy(pay).to("cuda"), P)
+        torch.cuda.synchronize()
+        want = oracle.hash_partition(keys[skip:], pay, P)
+        for g, w in zip((host(ko), host(vo), host(off)), want):
+            assert np.array_equal(g, w)
