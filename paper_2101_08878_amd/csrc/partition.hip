@@ -16,6 +16,10 @@
 //                   consecutive lanes on consecutive addresses.
 // A row's output position is off[p] + (rows of p in earlier tiles) + (rows
 // of p earlier in this tile), which is the stable counting-sort position.
+//
+// A merge runs each step once for its two tables, and splits every bucket
+// again with the segmented pass below (seg_*), whose histogram counts digit
+// bytes the first scatter wrote beside its rows.
 #include "mdx_internal.hpp"
 
 namespace mdx {
@@ -285,21 +289,27 @@ __device__ __forceinline__ void scatter_tile(const K *__restrict__ keys,
     int64_t *scratch = (int64_t *)(smem + L.scratch);
 
     const int tid = threadIdx.x, w = tid / kWave, lane = tid & (kWave - 1);
-    for (int i = tid; i < kWavesPerBlock * D; i += kBlock)
-        whist[i] = 0;
-    for (int p = tid; p < D; p += kBlock)
-        gbase[p] = base_of(p);
 
+    // The row loads go first (keys, then payloads, which are needed only
+    // for staging), so that the destination bases' loads and the ranking
+    // overlap them.
     const int64_t wrow0 = row0 + (int64_t)w * kWave * R;
     K kr[R];
     int64_t vr[R];
 #pragma unroll
     for (int c = 0; c < R; ++c) {
         const int64_t r = wrow0 + (int64_t)c * kWave + lane;
-        const bool valid = r < row_end;
-        kr[c] = valid ? __builtin_nontemporal_load(keys + r) : K(0);
-        vr[c] = valid ? __builtin_nontemporal_load(pay + r) : 0;
+        kr[c] = r < row_end ? __builtin_nontemporal_load(keys + r) : K(0);
     }
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+        const int64_t r = wrow0 + (int64_t)c * kWave + lane;
+        vr[c] = r < row_end ? __builtin_nontemporal_load(pay + r) : 0;
+    }
+    for (int i = tid; i < kWavesPerBlock * D; i += kBlock)
+        whist[i] = 0;
+    for (int p = tid; p < D; p += kBlock)
+        gbase[p] = base_of(p);
     __syncthreads();
 
     // Rank every row among the earlier rows of its wave with its destination.
