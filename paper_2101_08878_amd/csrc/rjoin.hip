@@ -24,6 +24,8 @@
 // while the build rows are inserted, and the hash chains of a thread's probe
 // rows are walked four at a time without branches, so that their LDS reads
 // are in flight together.
+#include <algorithm>
+
 #include "mdx.h"
 #include "mdx_internal.hpp"
 
@@ -383,7 +385,8 @@ hipError_t launch_rjoin_plan(const int64_t *subL, const int64_t *subR, int64_t S
                              const RJoinWs &w, hipStream_t s)
 {
     (void)subR;
-    const int G = device_fill_blocks() / 8 > 0 ? device_fill_blocks() / 8 : 1;
+    const int64_t cus = device_fill_blocks() / 8 > 0 ? device_fill_blocks() / 8 : 1;
+    const int G = (int)std::min<int64_t>(cus, (S + kBlock - 1) / kBlock + 1);
     hipLaunchKernelGGL(rj_plan_init, dim3(1), dim3(1), 0, s, w);
     hipLaunchKernelGGL(rj_plan, dim3(G), dim3(kBlock), 0, s, subL, S, w);
     return hipGetLastError();
@@ -396,8 +399,11 @@ hipError_t launch_rjoin(const void *lk, const int64_t *lv, const int64_t *subL, 
 {
     (void)P;
     (void)qbits;
-    const int cus = device_fill_blocks() / 8 > 0 ? device_fill_blocks() / 8 : 1;
-    const int G = cus * kJoinPerCu;  // all resident at once
+    // One workgroup per CU (all resident at once), or one per sub-bucket when
+    // there are fewer: a workgroup holds a CU's LDS, which other merges'
+    // kernels may need meanwhile.
+    const int64_t cus = device_fill_blocks() / 8 > 0 ? device_fill_blocks() / 8 : 1;
+    const int G = (int)std::max<int64_t>(1, std::min<int64_t>(cus * kJoinPerCu, w.S));
     trace_begin("rj_join", s);
     if (key_bytes == 8)
         hipLaunchKernelGGL(rj_join<int64_t>, dim3(G), dim3(kJoinThreads), 0, s,
