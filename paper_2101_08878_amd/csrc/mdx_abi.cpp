@@ -406,19 +406,22 @@ namespace {
 
 // How mdx_merge splits partitions into sub-buckets for the radix join: each
 // partition into Q = 2^qbits sub-buckets by the top hash bits, sized so that
-// an average sub-bucket's build rows fill ~80% of an LDS table.  The first
-// pass partitions by (p, top q1bits) with a fan-out of at most 128 (long,
-// coalesced output runs); the segmented second pass splits each of those
-// buckets by the next q2bits (at most 256 ways).
+// an average sub-bucket of the larger side fills ~80% of an LDS table: the
+// build side's rows must fit the table, and the probe side's should fit one
+// probe batch (with sub-buckets sized by a small build side alone, a large
+// probe side would leave a few workgroups looping over many batches each).
+// The first pass partitions by (p, top q1bits) with a fan-out of at most 128
+// (long, coalesced output runs); the segmented second pass splits each of
+// those buckets by the next q2bits (at most 256 ways).
 struct MergePlan {
     int qbits, q1bits, q2bits;
 };
 
-MergePlan merge_plan(int64_t nL, int32_t P)
+MergePlan merge_plan(int64_t nL, int64_t nR, int32_t P)
 {
     MergePlan m;
     const double per = 0.8 * kJoinCap;
-    const double want = (double)nL / ((double)P * per);
+    const double want = (double)std::max(nL, nR) / ((double)P * per);
     m.qbits = want <= 1.0 ? 0 : ceil_log2((int64_t)(want + 0.999999));
     // keep the sub-bucket count bounded; oversized sub-buckets fall back to
     // the global-table join
@@ -456,7 +459,7 @@ struct MergeLayout {
 MergeLayout merge_layout(int64_t nL, int64_t nR, int32_t P, int32_t kt)
 {
     MergeLayout M;
-    M.plan = merge_plan(nL, P);
+    M.plan = merge_plan(nL, nR, P);
     M.nA = (int64_t)P << M.plan.q1bits;
     M.S = (int64_t)P << M.plan.qbits;
     M.pl = part_layout(nL, (int32_t)M.nA);
