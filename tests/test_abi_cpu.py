@@ -201,6 +201,24 @@ def test_batch_validation():
     assert L._batch(2, None, 2, ws, need, None) == mdx.MDX_ERR_INVALID
 
 
+def test_merge_workspace_monotone_in_both_sides():
+    """A server slot and a batch lane are sized at the largest merge they
+    take, which covers every smaller one only if a merge's workspace never
+    shrinks as either side grows (the sub-bucket split depends on the larger
+    side)."""
+    sizes = [0, 1, 500, 7_680, 7_681, 10**4, 5 * 10**4, 10**5, 3 * 10**5, 10**6, 4 * 10**6,
+             2 * 10**7, 10**8]
+    for P in (1, 3, 8, 32, 257):
+        for kt in (4, 8):
+            ws = [[mdx.mdx_merge_workspace_bytes(a, b, P, kt) for b in sizes] for a in sizes]
+            for i in range(len(sizes)):
+                for j in range(len(sizes)):
+                    if i + 1 < len(sizes):
+                        assert ws[i + 1][j] >= ws[i][j], (P, kt, sizes[i], sizes[j])
+                    if j + 1 < len(sizes):
+                        assert ws[i][j + 1] >= ws[i][j], (P, kt, sizes[i], sizes[j])
+
+
 def test_server_workspace_and_validation():
     """Server sizing and every argument check that runs before a stream or
     event is created (no GPU needed)."""
