@@ -486,8 +486,8 @@ MergeLayout merge_layout(int64_t nL, int64_t nR, int32_t P, int32_t kt)
     take(M.offAR_off, (size_t)(M.nA + 1) * 8);
     take(M.offPL_off, (size_t)(P + 1) * 8);
     take(M.offPR_off, (size_t)(P + 1) * 8);
-    take(M.digL_off, two ? kL : 0);
-    take(M.digR_off, two ? kR : 0);
+    take(M.digL_off, two ? kL + 4 : 0);  // + 4: read as 4-byte words
+    take(M.digR_off, two ? kR + 4 : 0);
     take(M.segL_off, two ? M.sl.bytes : 0);
     take(M.segR_off, two ? M.sr.bytes : 0);
     take(M.lk2_off, two ? kL * kt : 0);

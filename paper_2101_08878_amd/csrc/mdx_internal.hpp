@@ -132,7 +132,8 @@ inline SegLayout seg_layout(int64_t n, int64_t nseg, int bits)
 }
 
 // One table of a segmented launch: dig holds every row's
-// digit_of(h, shift, bits), one byte per row (bits <= 8); segoff has nseg + 1
+// digit_of(h, shift, bits), one byte per row (bits <= 8), 4-byte aligned and
+// readable 4 bytes past its end (it is read as words); segoff has nseg + 1
 // entries, outoff nseg 2^bits + 1; ws holds seg_layout(n, nseg, bits).bytes.
 struct SegArgs {
     const void *keys;

@@ -482,13 +482,13 @@ __global__ __launch_bounds__(kBlock) void seg_plan(SegPair<K> T, int nseg)
 // per-tile digit counts, stored as the exclusive prefix over the chunk's
 // earlier tiles; chunk totals to csum.  The digits are the bytes the first
 // pass wrote beside its output rows, so this pass reads one byte per row
-// instead of the key.  All of the chunk's bytes are loaded at once, then
-// counted into one LDS histogram per tile.
+// instead of the key.  All of the chunk's bytes are loaded at once, four
+// per load, then counted into one LDS histogram per tile.
 template <typename K>
 __global__ __launch_bounds__(kBlock) void seg_hist(SegPair<K> T, int nseg, int bits)
 {
     __shared__ uint32_t hist[kSegChunkTiles][kSegMaxDest];
-    constexpr uint32_t kNone = 0xffffffffu;
+    static_assert(kSegTile == 4096, "tile of a row: (r - r0) >> 12");
     const bool second = (int64_t)blockIdx.x >= T.t[0].max_chunks;
     const SegTable<K> tb = pick(T, second);
     const int64_t c = second ? (int64_t)blockIdx.x - T.t[0].max_chunks : (int64_t)blockIdx.x;
@@ -501,19 +501,32 @@ __global__ __launch_bounds__(kBlock) void seg_hist(SegPair<K> T, int nseg, int b
     const int nt = (int)(t0 + kSegChunkTiles < tb.tile_start[a + 1] ? kSegChunkTiles
                                                                     : tb.tile_start[a + 1] - t0);
     const int64_t r0 = tb.segoff[a] + (t0 - tb.tile_start[a]) * kSegTile;  // chunk's first row
+    const int64_t r1 = r0 + kSegChunkTiles * kSegTile < s1 ? r0 + kSegChunkTiles * kSegTile : s1;
     for (int i = tid; i < kSegChunkTiles * kSegMaxDest; i += kBlock)
         (&hist[0][0])[i] = 0;
-    uint32_t dg[kSegChunkTiles * kSegRows];
+    // The chunk's bytes as aligned 4-byte words: thread tid takes words
+    // w0 + tid + j kBlock; a byte at row r counts toward tile (r - r0) / 4096
+    // when r0 <= r < r1 (the digit array has 4 bytes of slack past its end).
+    constexpr int kWords = (kSegChunkTiles * kSegTile / 4) / kBlock + 1;  // 17
+    const int64_t w0 = r0 >> 2, w1 = (r1 + 3) >> 2;
+    const uint32_t *words = (const uint32_t *)tb.dig;
+    uint32_t dw[kWords];
 #pragma unroll
-    for (int j = 0; j < kSegChunkTiles * kSegRows; ++j) {
-        const int64_t r = r0 + (int64_t)j * kBlock + tid;  // tile j / kSegRows
-        dg[j] = r < s1 ? (uint32_t)__builtin_nontemporal_load(tb.dig + r) : kNone;
+    for (int j = 0; j < kWords; ++j) {
+        const int64_t wi = w0 + tid + (int64_t)j * kBlock;
+        dw[j] = wi < w1 ? __builtin_nontemporal_load(words + wi) : 0u;
     }
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < kSegChunkTiles * kSegRows; ++j)
-        if (dg[j] != kNone)
-            atomicAdd(&hist[j / kSegRows][dg[j]], 1u);
+    for (int j = 0; j < kWords; ++j) {
+        const int64_t wi = w0 + tid + (int64_t)j * kBlock;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int64_t r = 4 * wi + b;
+            if (r >= r0 && r < r1)
+                atomicAdd(&hist[(r - r0) >> 12][(dw[j] >> (8 * b)) & 0xffu], 1u);
+        }
+    }
     __syncthreads();
     for (int q = tid; q < D; q += kBlock) {
         uint32_t run = 0;

@@ -76,6 +76,42 @@ __global__ void rj_plan_init(RJoinWs w)
     *w.use = 1;
 }
 
+// One block for the whole plan when there are few sub-buckets: the flag is
+// decided by a block-wide OR, so it needs no earlier kernel to set it.
+constexpr int kPlanOnePerThread = 8;
+
+__global__ __launch_bounds__(kBlock) void rj_plan_one(const int64_t *__restrict__ subL, int64_t S,
+                                                      RJoinWs w)
+{
+    // Every thread's loads are issued together: indices past S are clamped
+    // to S - 1 (S >= 1) and their results ignored, so no load sits behind a
+    // branch.
+    int64_t a[kPlanOnePerThread], b[kPlanOnePerThread];
+#pragma unroll
+    for (int k = 0; k < kPlanOnePerThread; ++k) {
+        const int64_t s = threadIdx.x + (int64_t)k * kBlock;
+        const int64_t c = s < S ? s : S - 1;
+        a[k] = subL[c];
+        b[k] = subL[c + 1];
+    }
+    int over = 0;
+#pragma unroll
+    for (int k = 0; k < kPlanOnePerThread; ++k) {
+        const int64_t s = threadIdx.x + (int64_t)k * kBlock;
+        over |= s < S && b[k] - a[k] > kJoinCap;
+        if (s < S)
+            w.status[s] = 0;
+    }
+    over = __syncthreads_or(over);
+    if (threadIdx.x == 0) {
+        *w.use = over ? 0 : 1;
+        *w.ticket = 0;
+    }
+}
+
+// Sub-buckets up to which rj_plan_one runs.
+constexpr int64_t kPlanOneMax = (int64_t)kBlock * kPlanOnePerThread;
+
 // This thread's rows of the batch starting at rb: rb + j * kJoinThreads + tid.
 template <typename K>
 __device__ __forceinline__ void load_batch(const K *__restrict__ rk, const int64_t *__restrict__ rv,
@@ -385,6 +421,10 @@ hipError_t launch_rjoin_plan(const int64_t *subL, const int64_t *subR, int64_t S
                              const RJoinWs &w, hipStream_t s)
 {
     (void)subR;
+    if (S <= kPlanOneMax) {
+        hipLaunchKernelGGL(rj_plan_one, dim3(1), dim3(kBlock), 0, s, subL, S, w);
+        return hipGetLastError();
+    }
     const int64_t cus = device_fill_blocks() / 8 > 0 ? device_fill_blocks() / 8 : 1;
     const int G = (int)std::min<int64_t>(cus, (S + kBlock - 1) / kBlock + 1);
     hipLaunchKernelGGL(rj_plan_init, dim3(1), dim3(1), 0, s, w);
