@@ -109,7 +109,7 @@ constexpr int kSegMaxDest = 256;
 
 struct SegLayout {
     int64_t max_tiles, max_chunks;
-    size_t tile_start_off, chunk_start_off, cnt_off, csum_off, bytes;
+    size_t tile_start_off, chunk_start_off, cnt_off, csum_off, tile_seg_off, chunk_seg_off, bytes;
 };
 
 inline SegLayout seg_layout(int64_t n, int64_t nseg, int bits)
@@ -127,6 +127,10 @@ inline SegLayout seg_layout(int64_t n, int64_t nseg, int bits)
     o += align_up((size_t)L.max_tiles * D * sizeof(uint32_t));
     L.csum_off = o;
     o += align_up((size_t)L.max_chunks * D * sizeof(int64_t));
+    L.tile_seg_off = o;
+    o += align_up((size_t)L.max_tiles * sizeof(uint32_t));
+    L.chunk_seg_off = o;
+    o += align_up((size_t)L.max_chunks * sizeof(uint32_t));
     L.bytes = o;
     return L;
 }

@@ -418,6 +418,8 @@ struct SegTable {
     uint32_t *cnt;           // [max_tiles][D]
     int64_t *csum;           // [max_chunks][D]
     int64_t *outoff;         // [nseg D + 1]
+    uint32_t *tile_seg;      // [max_tiles]: segment of every tile
+    uint32_t *chunk_seg;     // [max_chunks]: segment of every chunk
     K *keys_out;
     int64_t *pay_out;
     int64_t max_tiles, max_chunks;
@@ -442,6 +444,8 @@ __device__ __forceinline__ SegTable<K> pick(const SegPair<K> &T, bool second)
     r.cnt = second ? b.cnt : a.cnt;
     r.csum = second ? b.csum : a.csum;
     r.outoff = second ? b.outoff : a.outoff;
+    r.tile_seg = second ? b.tile_seg : a.tile_seg;
+    r.chunk_seg = second ? b.chunk_seg : a.chunk_seg;
     r.keys_out = second ? b.keys_out : a.keys_out;
     r.pay_out = second ? b.pay_out : a.pay_out;
     r.max_tiles = second ? b.max_tiles : a.max_tiles;
@@ -449,7 +453,9 @@ __device__ __forceinline__ SegTable<K> pick(const SegPair<K> &T, bool second)
     return r;
 }
 
-// Block t: tile and chunk starts of every segment of table t.
+// Block t: tile and chunk starts of every segment of table t, and the
+// segment of every tile and chunk (so that a tile or chunk finds its segment
+// with one load instead of a search over the starts).
 template <typename K>
 __global__ __launch_bounds__(kBlock) void seg_plan(SegPair<K> T, int nseg)
 {
@@ -468,6 +474,10 @@ __global__ __launch_bounds__(kBlock) void seg_plan(SegPair<K> T, int nseg)
         if (a < nseg) {
             tb.tile_start[a] = tcarry + te;
             tb.chunk_start[a] = ccarry + ce;
+            for (int64_t t = 0; t < nt; ++t)
+                tb.tile_seg[tcarry + te + t] = (uint32_t)a;
+            for (int64_t c = 0; c < nc; ++c)
+                tb.chunk_seg[ccarry + ce + c] = (uint32_t)a;
         }
         tcarry += tt;
         ccarry += ct;
@@ -492,10 +502,11 @@ __global__ __launch_bounds__(kBlock) void seg_hist(SegPair<K> T, int nseg, int b
     const bool second = (int64_t)blockIdx.x >= T.t[0].max_chunks;
     const SegTable<K> tb = pick(T, second);
     const int64_t c = second ? (int64_t)blockIdx.x - T.t[0].max_chunks : (int64_t)blockIdx.x;
-    if (c >= tb.chunk_start[nseg])
+    const int64_t nchunks = tb.chunk_start[nseg];
+    const int a = (int)tb.chunk_seg[c];  // meaningful when c < nchunks
+    if (c >= nchunks)
         return;
     const int D = 1 << bits, tid = threadIdx.x;
-    const int a = upper_index(tb.chunk_start, 0, nseg, c);
     const int64_t s1 = tb.segoff[a + 1];
     const int64_t t0 = tb.tile_start[a] + (c - tb.chunk_start[a]) * kSegChunkTiles;
     const int nt = (int)(t0 + kSegChunkTiles < tb.tile_start[a + 1] ? kSegChunkTiles
@@ -584,10 +595,11 @@ __global__ __launch_bounds__(kBlock) void seg_scatter(SegPair<K> T, int nseg, in
     const bool second = g >= T.t[0].max_tiles;
     const SegTable<K> tb = pick(T, second);
     const int64_t t = second ? g - T.t[0].max_tiles : g;
-    if (t >= tb.tile_start[nseg])
+    const int64_t ntiles = tb.tile_start[nseg];
+    const int a = (int)tb.tile_seg[t];  // meaningful when t < ntiles
+    if (t >= ntiles)
         return;
     const int D = 1 << bits;
-    const int a = upper_index(tb.tile_start, 0, nseg, t);
     const int64_t lt = t - tb.tile_start[a];
     const int64_t chunk = tb.chunk_start[a] + lt / kSegChunkTiles;
     const int64_t r0 = tb.segoff[a] + lt * kSegTile;
@@ -671,6 +683,8 @@ hipError_t run_seg_partition(const SegArgs *tables, int ntables, int64_t nseg, i
         t.cnt = (uint32_t *)(b + L.cnt_off);
         t.csum = (int64_t *)(b + L.csum_off);
         t.outoff = a.outoff;
+        t.tile_seg = (uint32_t *)(b + L.tile_seg_off);
+        t.chunk_seg = (uint32_t *)(b + L.chunk_seg_off);
         t.keys_out = (K *)a.keys_out;
         t.pay_out = a.pay_out;
         t.max_tiles = L.max_tiles;
