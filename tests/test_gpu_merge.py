@@ -59,21 +59,38 @@ def test_merge_repeated_keys_radix(dtype):
 
 
 @pytest.mark.parametrize("nl,nr,frac,P,dtype", [
-    (3_000, 200_000, 0.5, 2, np.int64),   # a sub-bucket's probe rows span 13 batches
+    (3_000, 200_000, 0.5, 2, np.int64),   # small build side, large probe side
     (6_000, 8_000, 1.0, 1, np.int64),     # one sub-bucket, every probe row matches
     (6_000, 8_000, 1.0, 1, np.int32),
     (6_000, 6_400, 1.0, 1, np.int64),
 ])
 def test_merge_join_routes(nl, nr, frac, P, dtype):
-    """Sub-buckets whose probe rows span several batches (looked up again
-    for the output) and sub-buckets with many output rows, against the
-    oracle."""
+    """Uneven sides and sub-buckets where every probe row matches, against
+    the oracle."""
     announce(f"merge routes {nl}x{nr} f={frac} P={P} {np.dtype(dtype).name}")
     kl, vl, kr, vr = match_fraction_tables(nl, nr, frac, seed=nl + nr, key_dtype=dtype)
     total = oracle.join(kl, vl, kr, vr, materialize=False)["total"]
     got = run_merge(kl, vl, kr, vr, P, cap=total)
     assert got["status"] == 0
     assert_join_equals_oracle(kl, vl, kr, vr, P, got)
+
+
+def test_merge_probe_sub_bucket_spans_batches():
+    """One probe key repeated 20000 times: its sub-bucket holds more probe
+    rows than one 8192-row batch, so the join counts and then writes it
+    batch by batch (sub-buckets are sized by the larger side, so only a
+    repeated probe key gets there)."""
+    announce("merge probe key x 20000")
+    rng = np.random.default_rng(21)
+    kl = rng.permutation(50_000).astype(np.int64)
+    kr = np.concatenate([np.full(20_000, 777, np.int64), rng.integers(0, 100_000, 30_000)])
+    kr = kr[rng.permutation(kr.size)]
+    vl, vr = np.arange(kl.size, dtype=np.int64), np.arange(kr.size, dtype=np.int64)
+    total = oracle.join(kl, vl, kr, vr, materialize=False)["total"]
+    for P in (1, 4):
+        got = run_merge(kl, vl, kr, vr, P, cap=total)
+        assert got["status"] == 0
+        assert_join_equals_oracle(kl, vl, kr, vr, P, got)
 
 
 def test_merge_some_sub_buckets_repeat_keys():
