@@ -460,7 +460,9 @@ template <typename K>
 __global__ __launch_bounds__(kBlock) void seg_plan(SegPair<K> T, int nseg)
 {
     __shared__ int64_t scratch[kWavesPerBlock];
+    __shared__ int64_t ts[kBlock + 1], cs[kBlock + 1];  // starts, when nseg <= kBlock
     const SegTable<K> tb = pick(T, blockIdx.x != 0);
+    const bool few = nseg <= kBlock;
     int64_t tcarry = 0, ccarry = 0;
     for (int base = 0; base < nseg; base += kBlock) {
         const int a = base + threadIdx.x;
@@ -474,10 +476,15 @@ __global__ __launch_bounds__(kBlock) void seg_plan(SegPair<K> T, int nseg)
         if (a < nseg) {
             tb.tile_start[a] = tcarry + te;
             tb.chunk_start[a] = ccarry + ce;
-            for (int64_t t = 0; t < nt; ++t)
-                tb.tile_seg[tcarry + te + t] = (uint32_t)a;
-            for (int64_t c = 0; c < nc; ++c)
-                tb.chunk_seg[ccarry + ce + c] = (uint32_t)a;
+            if (few) {
+                ts[a] = te;
+                cs[a] = ce;
+            } else {  // one thread per segment writes its entries
+                for (int64_t t = 0; t < nt; ++t)
+                    tb.tile_seg[tcarry + te + t] = (uint32_t)a;
+                for (int64_t c = 0; c < nc; ++c)
+                    tb.chunk_seg[ccarry + ce + c] = (uint32_t)a;
+            }
         }
         tcarry += tt;
         ccarry += ct;
@@ -485,6 +492,20 @@ __global__ __launch_bounds__(kBlock) void seg_plan(SegPair<K> T, int nseg)
     if (threadIdx.x == 0) {
         tb.tile_start[nseg] = tcarry;
         tb.chunk_start[nseg] = ccarry;
+        if (few) {
+            ts[nseg] = tcarry;
+            cs[nseg] = ccarry;
+        }
+    }
+    if (!few)
+        return;
+    // Few segments: the whole block writes one segment's entries at a time.
+    __syncthreads();
+    for (int a = 0; a < nseg; ++a) {
+        for (int64_t t = ts[a] + threadIdx.x; t < ts[a + 1]; t += kBlock)
+            tb.tile_seg[t] = (uint32_t)a;
+        for (int64_t c = cs[a] + threadIdx.x; c < cs[a + 1]; c += kBlock)
+            tb.chunk_seg[c] = (uint32_t)a;
     }
 }
 
