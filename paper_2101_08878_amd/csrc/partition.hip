@@ -454,15 +454,13 @@ __device__ __forceinline__ SegTable<K> pick(const SegPair<K> &T, bool second)
 }
 
 // Block t: tile and chunk starts of every segment of table t, and the
-// segment of every tile and chunk (so that a tile or chunk finds its segment
-// with one load instead of a search over the starts).
+// segment of every chunk (a chunk then finds its segment with one load
+// instead of a search over the starts; seg_scan writes the same for tiles).
 template <typename K>
 __global__ __launch_bounds__(kBlock) void seg_plan(SegPair<K> T, int nseg)
 {
     __shared__ int64_t scratch[kWavesPerBlock];
-    __shared__ int64_t ts[kBlock + 1], cs[kBlock + 1];  // starts, when nseg <= kBlock
     const SegTable<K> tb = pick(T, blockIdx.x != 0);
-    const bool few = nseg <= kBlock;
     int64_t tcarry = 0, ccarry = 0;
     for (int base = 0; base < nseg; base += kBlock) {
         const int a = base + threadIdx.x;
@@ -476,15 +474,8 @@ __global__ __launch_bounds__(kBlock) void seg_plan(SegPair<K> T, int nseg)
         if (a < nseg) {
             tb.tile_start[a] = tcarry + te;
             tb.chunk_start[a] = ccarry + ce;
-            if (few) {
-                ts[a] = te;
-                cs[a] = ce;
-            } else {  // one thread per segment writes its entries
-                for (int64_t t = 0; t < nt; ++t)
-                    tb.tile_seg[tcarry + te + t] = (uint32_t)a;
-                for (int64_t c = 0; c < nc; ++c)
-                    tb.chunk_seg[ccarry + ce + c] = (uint32_t)a;
-            }
+            for (int64_t c = 0; c < nc; ++c)
+                tb.chunk_seg[ccarry + ce + c] = (uint32_t)a;
         }
         tcarry += tt;
         ccarry += ct;
@@ -492,20 +483,6 @@ __global__ __launch_bounds__(kBlock) void seg_plan(SegPair<K> T, int nseg)
     if (threadIdx.x == 0) {
         tb.tile_start[nseg] = tcarry;
         tb.chunk_start[nseg] = ccarry;
-        if (few) {
-            ts[nseg] = tcarry;
-            cs[nseg] = ccarry;
-        }
-    }
-    if (!few)
-        return;
-    // Few segments: the whole block writes one segment's entries at a time.
-    __syncthreads();
-    for (int a = 0; a < nseg; ++a) {
-        for (int64_t t = ts[a] + threadIdx.x; t < ts[a + 1]; t += kBlock)
-            tb.tile_seg[t] = (uint32_t)a;
-        for (int64_t c = cs[a] + threadIdx.x; c < cs[a + 1]; c += kBlock)
-            tb.chunk_seg[c] = (uint32_t)a;
     }
 }
 
@@ -571,7 +548,8 @@ __global__ __launch_bounds__(kBlock) void seg_hist(SegPair<K> T, int nseg, int b
 }
 
 // Block = segment (nseg blocks per table): chunk totals -> exclusive prefix
-// over the segment's chunks (in place); destination bases outoff[a D + q].
+// over the segment's chunks (in place); destination bases outoff[a D + q];
+// the segment of each of the segment's tiles.
 template <typename K>
 __global__ __launch_bounds__(kBlock) void seg_scan(SegPair<K> T, int nseg, int bits)
 {
@@ -581,6 +559,8 @@ __global__ __launch_bounds__(kBlock) void seg_scan(SegPair<K> T, int nseg, int b
     const SegTable<K> tb = pick(T, second);
     const int a = second ? (int)blockIdx.x - nseg : (int)blockIdx.x;
     const int D = 1 << bits, tid = threadIdx.x;
+    for (int64_t t = tb.tile_start[a] + tid; t < tb.tile_start[a + 1]; t += kBlock)
+        tb.tile_seg[t] = (uint32_t)a;
     const int64_t c0 = tb.chunk_start[a], c1 = tb.chunk_start[a + 1];
     for (int q = tid; q < D; q += kBlock) {
         int64_t run = 0;
