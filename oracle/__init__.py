@@ -37,6 +37,9 @@ def _load():
     lib.oracle_join.argtypes = [vp, vp, i64, vp, vp, i64, i32, vp, vp, vp, i64, i32, vp]
     lib.oracle_match_counts.restype = i32
     lib.oracle_match_counts.argtypes = [vp, i64, vp, i64, i32, vp]
+    lib.oracle_merge_threads.restype = i64
+    lib.oracle_merge_threads.argtypes = [vp, vp, i64, vp, vp, i64, i32, i32, i32, vp, vp, vp,
+                                         vp, vp, vp, vp, vp, vp, i64, vp]
     _lib = lib
     return lib
 
@@ -123,6 +126,37 @@ def match_counts(lkeys, rkeys) -> np.ndarray:
     if rc != 0:
         raise ValueError("oracle_match_counts failed")
     return out
+
+
+def merge_threads(lkeys, lpay, rkeys, rpay, P: int, threads: int, cap: int | None = None):
+    """Both partitions and the per-destination join, over `threads` host
+    threads (the CPU baseline's all-cores leg).
+
+    Returns dict(left=(keys, payload, off), right=(...), out_off[P+1],
+    total, and key/lpay/rpay in the join walk's order when |J| <= cap).
+    """
+    lk, rk = _keys(lkeys), _keys(rkeys)
+    if lk.dtype != rk.dtype:
+        raise TypeError("left and right keys must have the same dtype")
+    lv = np.ascontiguousarray(lpay, dtype=np.int64)
+    rv = np.ascontiguousarray(rpay, dtype=np.int64)
+    nl, nr = lk.size, rk.size
+    lko, rko = np.empty_like(lk), np.empty_like(rk)
+    lvo, rvo = np.empty(nl, np.int64), np.empty(nr, np.int64)
+    loff, roff, out_off = (np.empty(P + 1, np.int64) for _ in range(3))
+    cap = nr if cap is None else int(cap)
+    ok, ol, orr = (np.empty(max(cap, 1), np.int64) for _ in range(3))
+    total = _load().oracle_merge_threads(
+        _ptr(lk), _ptr(lv), nl, _ptr(rk), _ptr(rv), nr, lk.dtype.itemsize, int(P), int(threads),
+        _ptr(lko), _ptr(lvo), _ptr(loff), _ptr(rko), _ptr(rvo), _ptr(roff),
+        _ptr(ok), _ptr(ol), _ptr(orr), cap, _ptr(out_off))
+    if total < 0:
+        raise ValueError("oracle_merge_threads failed")
+    res = {"left": (lko, lvo, loff), "right": (rko, rvo, roff), "out_off": out_off,
+           "total": int(total)}
+    if total <= cap:
+        res.update(key=ok[:total], lpay=ol[:total], rpay=orr[:total])
+    return res
 
 
 def transpose_sum(x) -> np.ndarray:

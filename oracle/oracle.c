@@ -30,7 +30,9 @@
  * fmix64(0) = 0; numpy's stable argsort for the partition; nested-loop brute
  * force and pandas.merge for the join; closed-form cardinalities.
  */
+#define _POSIX_C_SOURCE 200809L /* pthread barriers under -std=c11 */
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -280,4 +282,261 @@ int32_t oracle_match_counts(const void *lkeys, int64_t nl, const void *rkeys, in
     }
     free(L);
     return 0;
+}
+
+/* ---- the same two steps over several host threads (CPU baseline) -------- */
+
+/* What the benchmark times beside the GPU: the partition and the join above,
+ * spread over T host threads, with the same result.
+ *
+ * Partition, per table: the rows are cut into T contiguous blocks; thread b
+ * counts its block's rows per destination; the first position of
+ * (destination p, block b) is off[p] plus the rows of p in the blocks before
+ * b -- the counting sort's prefix taken in (destination, block) order; then
+ * thread b places its block's rows in input order.  Every row lands where the
+ * one-thread counting sort puts it, so the partitions are identical.
+ *
+ * Join: destination p of the left table is joined with destination p of the
+ * right table (equal keys share a destination) by the sort-merge above, one
+ * destination at a time per thread: a walk that counts, a prefix over the
+ * destinations, and a walk that writes destination p's rows at
+ * [out_off[p], out_off[p+1]) in the walk's order (the canonical order is for
+ * comparisons only and is not produced here).  If |J| > cap, only out_off is
+ * written.  Returns |J|, or -1 on bad arguments or allocation failure. */
+
+#include <pthread.h>
+#include <stdatomic.h>
+
+typedef struct {
+    const void *keys;
+    const int64_t *pay;
+    int64_t n;
+    void *keys_out;
+    int64_t *pay_out;
+    int64_t *off;  /* [P + 1] */
+    int64_t *cnt;  /* [T][P]: rows of destination p in block b */
+    int64_t *base; /* [T][P]: first position of (p, b) */
+} ptab_t;
+
+typedef struct {
+    ptab_t tab[2]; /* left, right */
+    int32_t key_bytes, P, T;
+    kv_t **Ls, **Rs;   /* [P]: destination p's pairs, sorted */
+    int64_t *nLs, *nRs;
+    int64_t *jcnt;     /* [P]: |J_p| */
+    int64_t *out_off;  /* [P + 1] */
+    int64_t *out_key, *out_lpay, *out_rpay, cap;
+    atomic_int next_sort, next_write, failed;
+    pthread_barrier_t bar;
+} pmerge_t;
+
+typedef struct {
+    pmerge_t *m;
+    int32_t b;
+} pworker_t;
+
+static void ptab_count(const pmerge_t *m, ptab_t *t, int32_t b)
+{
+    const int64_t lo = t->n * b / m->T, hi = t->n * (b + 1) / m->T;
+    int64_t *c = t->cnt + (int64_t)b * m->P;
+    for (int32_t p = 0; p < m->P; p++)
+        c[p] = 0;
+    for (int64_t i = lo; i < hi; i++)
+        c[oracle_partition_of(key_at(t->keys, m->key_bytes, i), m->P)]++;
+}
+
+/* One thread: destination offsets and the (destination, block) bases. */
+static void ptab_bases(const pmerge_t *m, ptab_t *t)
+{
+    int64_t run = 0;
+    for (int32_t p = 0; p < m->P; p++) {
+        t->off[p] = run;
+        for (int32_t b = 0; b < m->T; b++) {
+            t->base[(int64_t)b * m->P + p] = run;
+            run += t->cnt[(int64_t)b * m->P + p];
+        }
+    }
+    t->off[m->P] = run;
+}
+
+static void ptab_place(const pmerge_t *m, ptab_t *t, int32_t b)
+{
+    const int64_t lo = t->n * b / m->T, hi = t->n * (b + 1) / m->T;
+    int64_t *cur = t->base + (int64_t)b * m->P;
+    for (int64_t i = lo; i < hi; i++) {
+        const int64_t k = key_at(t->keys, m->key_bytes, i);
+        const int64_t j = cur[oracle_partition_of(k, m->P)]++;
+        key_put(t->keys_out, m->key_bytes, j, k);
+        t->pay_out[j] = t->pay[i];
+    }
+}
+
+/* Destination p's (key, payload) pairs of a partitioned table, sorted. */
+static kv_t *ptab_pairs(const pmerge_t *m, const ptab_t *t, int32_t p, int64_t *cnt)
+{
+    const int64_t a = t->off[p], e = t->off[p + 1];
+    kv_t *x = malloc((size_t)(e > a ? e - a : 1) * sizeof(kv_t));
+    if (!x)
+        return NULL;
+    for (int64_t i = a; i < e; i++) {
+        x[i - a].k = key_at(t->keys_out, m->key_bytes, i);
+        x[i - a].v = t->pay_out[i];
+    }
+    qsort(x, (size_t)(e - a), sizeof(kv_t), cmp_kv);
+    *cnt = e - a;
+    return x;
+}
+
+/* Sort-merge walk of one destination: counts (w == NULL) or writes at w. */
+static int64_t pjoin_walk(const kv_t *L, int64_t nl, const kv_t *R, int64_t nr, int64_t *ok,
+                          int64_t *ol, int64_t *orr)
+{
+    int64_t w = 0;
+    for (int64_t i = 0, j = 0; i < nl && j < nr;) {
+        if (L[i].k < R[j].k) {
+            i++;
+        } else if (L[i].k > R[j].k) {
+            j++;
+        } else {
+            const int64_t k = L[i].k;
+            int64_t i2 = i, j2 = j;
+            while (i2 < nl && L[i2].k == k)
+                i2++;
+            while (j2 < nr && R[j2].k == k)
+                j2++;
+            if (ok) {
+                for (int64_t a = i; a < i2; a++)
+                    for (int64_t b = j; b < j2; b++) {
+                        ok[w] = k;
+                        ol[w] = L[a].v;
+                        orr[w] = R[b].v;
+                        w++;
+                    }
+            } else {
+                w += (i2 - i) * (j2 - j);
+            }
+            i = i2;
+            j = j2;
+        }
+    }
+    return w;
+}
+
+static void *pmerge_worker(void *arg)
+{
+    const pworker_t *wk = arg;
+    pmerge_t *m = wk->m;
+    const int32_t b = wk->b;
+    ptab_count(m, &m->tab[0], b);
+    ptab_count(m, &m->tab[1], b);
+    pthread_barrier_wait(&m->bar);
+    if (b == 0) {
+        ptab_bases(m, &m->tab[0]);
+        ptab_bases(m, &m->tab[1]);
+    }
+    pthread_barrier_wait(&m->bar);
+    ptab_place(m, &m->tab[0], b);
+    ptab_place(m, &m->tab[1], b);
+    pthread_barrier_wait(&m->bar);
+    for (int p; (p = atomic_fetch_add(&m->next_sort, 1)) < m->P;) {
+        m->Ls[p] = ptab_pairs(m, &m->tab[0], p, &m->nLs[p]);
+        m->Rs[p] = ptab_pairs(m, &m->tab[1], p, &m->nRs[p]);
+        if (!m->Ls[p] || !m->Rs[p]) {
+            atomic_store(&m->failed, 1);
+            m->jcnt[p] = 0;
+            continue;
+        }
+        m->jcnt[p] = pjoin_walk(m->Ls[p], m->nLs[p], m->Rs[p], m->nRs[p], NULL, NULL, NULL);
+    }
+    pthread_barrier_wait(&m->bar);
+    if (b == 0) {
+        int64_t run = 0;
+        for (int32_t p = 0; p < m->P; p++) {
+            m->out_off[p] = run;
+            run += m->jcnt[p];
+        }
+        m->out_off[m->P] = run;
+    }
+    pthread_barrier_wait(&m->bar);
+    const int fits = m->out_key && m->out_lpay && m->out_rpay && m->out_off[m->P] <= m->cap &&
+                     !atomic_load(&m->failed);
+    for (int p; (p = atomic_fetch_add(&m->next_write, 1)) < m->P;) {
+        if (fits) {
+            const int64_t o = m->out_off[p];
+            pjoin_walk(m->Ls[p], m->nLs[p], m->Rs[p], m->nRs[p], m->out_key + o, m->out_lpay + o,
+                       m->out_rpay + o);
+        }
+        free(m->Ls[p]);
+        free(m->Rs[p]);
+        m->Ls[p] = m->Rs[p] = NULL;
+    }
+    return NULL;
+}
+
+int64_t oracle_merge_threads(const void *lkeys, const int64_t *lpay, int64_t nl,
+                             const void *rkeys, const int64_t *rpay, int64_t nr,
+                             int32_t key_bytes, int32_t P, int32_t threads, void *lk_out,
+                             int64_t *lv_out, int64_t *loff, void *rk_out, int64_t *rv_out,
+                             int64_t *roff, int64_t *out_key, int64_t *out_lpay,
+                             int64_t *out_rpay, int64_t cap, int64_t *out_off)
+{
+    if (nl < 0 || nr < 0 || P < 1 || threads < 1 || threads > 1024 ||
+        (key_bytes != 4 && key_bytes != 8) || !loff || !roff || !out_off)
+        return -1;
+    pmerge_t *m = calloc(1, sizeof(pmerge_t));
+    pthread_t *th = calloc((size_t)threads, sizeof(pthread_t));
+    pworker_t *wk = calloc((size_t)threads, sizeof(pworker_t));
+    int64_t *cnt = calloc((size_t)4 * threads * P, sizeof(int64_t));
+    int64_t *per = calloc((size_t)3 * P, sizeof(int64_t));
+    kv_t **lists = calloc((size_t)2 * P, sizeof(kv_t *));
+    int64_t result = -1;
+    if (!m || !th || !wk || !cnt || !per || !lists)
+        goto done;
+    m->key_bytes = key_bytes;
+    m->P = P;
+    m->T = threads;
+    const ptab_t L = {lkeys, lpay, nl, lk_out, lv_out, loff, cnt, cnt + (int64_t)threads * P};
+    const ptab_t R = {rkeys, rpay, nr, rk_out, rv_out, roff, cnt + 2 * (int64_t)threads * P,
+                      cnt + 3 * (int64_t)threads * P};
+    m->tab[0] = L;
+    m->tab[1] = R;
+    m->Ls = lists;
+    m->Rs = lists + P;
+    m->nLs = per;
+    m->nRs = per + P;
+    m->jcnt = per + 2 * (int64_t)P;
+    m->out_off = out_off;
+    m->out_key = out_key;
+    m->out_lpay = out_lpay;
+    m->out_rpay = out_rpay;
+    m->cap = cap;
+    atomic_init(&m->next_sort, 0);
+    atomic_init(&m->next_write, 0);
+    atomic_init(&m->failed, 0);
+    if (pthread_barrier_init(&m->bar, NULL, (unsigned)threads) != 0)
+        goto done;
+    int32_t started = 0;
+    for (; started < threads; started++) {
+        wk[started].m = m;
+        wk[started].b = started;
+        if (pthread_create(&th[started], NULL, pmerge_worker, &wk[started]) != 0)
+            break;
+    }
+    if (started < threads) {
+        /* the barrier waits for every thread: without all of them none ends */
+        fputs("oracle_merge_threads: pthread_create failed\n", stderr);
+        abort();
+    }
+    for (int32_t t = 0; t < threads; t++)
+        pthread_join(th[t], NULL);
+    pthread_barrier_destroy(&m->bar);
+    result = atomic_load(&m->failed) ? -1 : out_off[P];
+done:
+    free(m);
+    free(th);
+    free(wk);
+    free(cnt);
+    free(per);
+    free(lists);
+    return result;
 }

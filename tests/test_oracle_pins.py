@@ -365,3 +365,59 @@ def test_transpose_sum_edge_shapes():
     assert oracle.transpose_sum(np.array([[2.5]]))[0, 0] == 5.0
     with pytest.raises(ValueError):
         oracle.transpose_sum(np.zeros((2, 3)))
+
+
+# --------------------------------------------------------------------------
+# the threaded CPU baseline (same partition and join over host threads)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("threads", [1, 3, 8])
+@pytest.mark.parametrize("P", [1, 4, 7, 32])
+def test_merge_threads_partitions_equal_stable_argsort(threads, P):
+    kl, vl, kr, vr = uniform_tables(3000, 2500, 1500, seed=P * 10 + threads)
+    res = oracle.merge_threads(kl, vl, kr, vr, P, threads)
+    for side, (k, v) in (("left", (kl, vl)), ("right", (kr, vr))):
+        want = _partition_by_argsort(k, v, P)
+        for g, w in zip(res[side], want):
+            assert np.array_equal(g, w)
+
+
+@pytest.mark.parametrize("threads", [1, 2, 5, 16])
+def test_merge_threads_join_equals_brute_force(threads):
+    kl, vl, kr, vr = uniform_tables(300, 280, 40, seed=threads)
+    vl, vr = vl * 3 + 11, vr * 7 - 5
+    res = oracle.merge_threads(kl, vl, kr, vr, 4, threads, cap=kl.size * kr.size)
+    want = brute_force_join(kl, vl, kr, vr)
+    assert res["total"] == want[0].size
+    for g, w in zip(canonical(res["key"], res["lpay"], res["rpay"]), want):
+        assert np.array_equal(g, w)
+    # destination p's rows sit at [out_off[p], out_off[p+1])
+    off = res["out_off"]
+    for p in range(4):
+        assert (part_np(res["key"][off[p]:off[p + 1]], 4) == p).all()
+
+
+def test_merge_threads_plain_workload_and_edges():
+    kl, vl, kr, vr = config_inputs("plain")
+    res = oracle.merge_threads(kl, vl, kr, vr, 4, 8)
+    ref = oracle.join(kl, vl, kr, vr, P=4)
+    assert res["total"] == ref["total"]
+    assert np.array_equal(np.diff(res["out_off"]), ref["per_part"])
+    for g, w in zip(canonical(res["key"], res["lpay"], res["rpay"]),
+                    (ref["key"], ref["lpay"], ref["rpay"])):
+        assert np.array_equal(g, w)
+    for name in ["empty_left", "both_empty", "all_equal", "int32_negative", "extremes"]:
+        kl, vl, kr, vr, _ = edge_tables(name)
+        kl, vl, kr, vr = kl[:300], vl[:300], kr[:300], vr[:300]
+        res = oracle.merge_threads(kl, vl, kr, vr, 5, 4, cap=kl.size * kr.size)
+        want = brute_force_join(kl, vl, kr, vr)
+        assert res["total"] == want[0].size, name
+        for g, w in zip(canonical(res["key"], res["lpay"], res["rpay"]), want):
+            assert np.array_equal(g, w), name
+
+
+def test_merge_threads_small_capacity_writes_offsets_only():
+    kl, vl, kr, vr = uniform_tables(500, 500, 50, seed=1)
+    want = expected_cardinality(kl, kr)
+    res = oracle.merge_threads(kl, vl, kr, vr, 4, 4, cap=want - 1)
+    assert res["total"] == want and res["out_off"][-1] == want and "key" not in res
