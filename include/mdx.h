@@ -19,7 +19,9 @@
  *    thread-local message.
  *  - All device memory is owned by the caller.  libmdx never allocates or
  *    frees device memory; buffers whose size depends on the data are bounded
- *    by a *_bytes() query that depends only on sizes (n, P, key type).
+ *    by a *_bytes() query that depends only on sizes (n, P, key type).  The
+ *    one exception is the fixed scratch array that the code object of
+ *    mdx_hash_partition_noalloc carries (see there).
  *  - Device pointers ("d_" prefix) must point to memory of the current HIP
  *    device and be aligned to 256 bytes where they are workspaces or tables,
  *    and to their element size otherwise.  Host pointers have an "h_" prefix.
@@ -123,6 +125,31 @@ int32_t mdx_hash_partition(const void *d_keys, const int64_t *d_payload, int64_t
                            int32_t key_type, int32_t P, void *d_keys_out,
                            int64_t *d_payload_out, int64_t *d_offsets, void *d_ws,
                            size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Hash partition without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).
+ *
+ * Computes exactly what mdx_hash_partition computes (same outputs, same
+ * arguments minus the workspace).  Its workspace is a device array inside
+ * the library of MDX_NOALLOC_SCRATCH_BYTES bytes: every GPU the library runs
+ * on holds one, from the first call on that GPU until the process ends.  The
+ * call itself allocates nothing (no hipMalloc, no allocating library call);
+ * the caller still passes the input and output buffers.
+ * Errors: as mdx_hash_partition, and MDX_ERR_WORKSPACE (nothing enqueued)
+ * when mdx_hash_partition_workspace_bytes(n, P, key_type) exceeds
+ * MDX_NOALLOC_SCRATCH_BYTES (e.g. n = 1E8 rows fits up to P = 85).
+ * Every call on one GPU uses that GPU's one array: calls that overlap on a
+ * GPU (different streams, or threads, without ordering between them) race
+ * and give wrong results; order them.
+ * ------------------------------------------------------------------------- */
+#define MDX_NOALLOC_SCRATCH_BYTES (16u << 20)
+
+int32_t mdx_hash_partition_noalloc(const void *d_keys, const int64_t *d_payload, int64_t n,
+                                   int32_t key_type, int32_t P, void *d_keys_out,
+                                   int64_t *d_payload_out, int64_t *d_offsets,
+                                   hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Join build: one hash table per partition of the build (left) table.

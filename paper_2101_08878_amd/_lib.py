@@ -38,6 +38,7 @@ MDX_DEV_BAD_PARTITIONING = 2
 MDX_DEV_SCAN_TIMEOUT = 4
 MDX_MAX_P = 4096
 MDX_MAX_LANES = 8
+MDX_NOALLOC_SCRATCH_BYTES = 16 << 20
 MDX_MAX_SLOTS = 32
 MDX_MAX_TRANSPOSE_N = 1 << 17
 
@@ -75,6 +76,8 @@ _status_string = _sig("mdx_status_string", ctypes.c_char_p, _i32)
 _last_error = _sig("mdx_last_error", ctypes.c_char_p)
 _part_ws = _sig("mdx_hash_partition_workspace_bytes", _i32, _i64, _i32, _i32, ctypes.POINTER(_sz))
 _part = _sig("mdx_hash_partition", _i32, _vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _sz, _vp)
+_part_noalloc = _sig("mdx_hash_partition_noalloc", _i32, _vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp,
+                     _vp)
 _table_bytes = _sig("mdx_join_table_bytes", _i32, _i64, _i32, _i32, ctypes.POINTER(_sz))
 _build = _sig("mdx_join_build", _i32, _vp, _vp, _vp, _i64, _i32, _i32, _vp, _sz,
               ctypes.POINTER(mdx_table), _vp, _vp)
@@ -104,7 +107,7 @@ _trace = _sig("mdx_trace_kernel", _i32, ctypes.c_char_p, _vp, _vp, _i32, ctypes.
 
 ABI_FUNCTIONS = [
     "mdx_abi_version", "mdx_status_string", "mdx_last_error",
-    "mdx_hash_partition_workspace_bytes", "mdx_hash_partition",
+    "mdx_hash_partition_workspace_bytes", "mdx_hash_partition", "mdx_hash_partition_noalloc",
     "mdx_join_table_bytes", "mdx_join_build",
     "mdx_join_probe_workspace_bytes", "mdx_join_probe",
     "mdx_merge_workspace_bytes", "mdx_merge",
@@ -203,6 +206,20 @@ def mdx_hash_partition(keys: torch.Tensor, payload: torch.Tensor, P: int, *, key
                  _dev(keys_out, "keys_out", keys.dtype, n), _dev(payload_out, "payload_out", torch.int64, n),
                  _dev(offsets, "offsets", torch.int64, P + 1), _dev(workspace, "workspace"),
                  workspace.numel() * workspace.element_size(), _stream(stream)))
+    return keys_out, payload_out, offsets
+
+
+def mdx_hash_partition_noalloc(keys: torch.Tensor, payload: torch.Tensor, P: int, *, keys_out,
+                               payload_out, offsets, stream=None):
+    """mdx_hash_partition with the library's own scratch array as its
+    workspace (for callers that cannot allocate).  The outputs are the
+    caller's; nothing is allocated here or in the call."""
+    n = keys.numel()
+    kt = _key_type(keys)
+    _check(_part_noalloc(_dev(keys, "keys"), _dev(payload, "payload", torch.int64, n), n, kt, int(P),
+                         _dev(keys_out, "keys_out", keys.dtype, n),
+                         _dev(payload_out, "payload_out", torch.int64, n),
+                         _dev(offsets, "offsets", torch.int64, P + 1), _stream(stream)))
     return keys_out, payload_out, offsets
 
 

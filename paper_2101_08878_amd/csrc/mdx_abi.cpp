@@ -202,12 +202,14 @@ int32_t mdx_hash_partition_workspace_bytes(int64_t n, int32_t P, int32_t key_typ
     return MDX_OK;
 }
 
-int32_t mdx_hash_partition(const void *d_keys, const int64_t *d_payload, int64_t n,
-                           int32_t key_type, int32_t P, void *d_keys_out, int64_t *d_payload_out,
-                           int64_t *d_offsets, void *d_ws, size_t ws_bytes, hipStream_t stream)
+}  // extern "C"
+
+// Host checks of a partition call's columns and offsets (W names the caller).
+static int32_t check_partition(const void *d_keys, const int64_t *d_payload, int64_t n,
+                               int32_t key_type, int32_t P, const void *d_keys_out,
+                               const int64_t *d_payload_out, const int64_t *d_offsets,
+                               const char *W)
 {
-    g_err.clear();
-    const char *W = "mdx_hash_partition";
     if (int32_t e = check_sizes(n, P, key_type, W))
         return e;
     if (int32_t e = check_columns(d_keys, d_payload, n, key_type, W))
@@ -215,12 +217,27 @@ int32_t mdx_hash_partition(const void *d_keys, const int64_t *d_payload, int64_t
     if (int32_t e = check_columns(d_keys_out, d_payload_out, n, key_type, W))
         return e;
     if (!d_offsets || !aligned(d_offsets, 8))
-        return fail(MDX_ERR_INVALID, "mdx_hash_partition: d_offsets null or misaligned");
+        return fail(MDX_ERR_INVALID, std::string(W) + ": d_offsets null or misaligned");
     const size_t kb = (size_t)n * key_type, vb = (size_t)n * 8;
     if (overlap(d_keys, kb, d_keys_out, kb) || overlap(d_keys, kb, d_payload_out, vb) ||
         overlap(d_payload, vb, d_keys_out, kb) || overlap(d_payload, vb, d_payload_out, vb) ||
         overlap(d_keys_out, kb, d_payload_out, vb))
-        return fail(MDX_ERR_INVALID, "mdx_hash_partition: output columns overlap inputs or each other");
+        return fail(MDX_ERR_INVALID,
+                    std::string(W) + ": output columns overlap inputs or each other");
+    return MDX_OK;
+}
+
+extern "C" {
+
+int32_t mdx_hash_partition(const void *d_keys, const int64_t *d_payload, int64_t n,
+                           int32_t key_type, int32_t P, void *d_keys_out, int64_t *d_payload_out,
+                           int64_t *d_offsets, void *d_ws, size_t ws_bytes, hipStream_t stream)
+{
+    g_err.clear();
+    const char *W = "mdx_hash_partition";
+    if (int32_t e = check_partition(d_keys, d_payload, n, key_type, P, d_keys_out, d_payload_out,
+                                    d_offsets, W))
+        return e;
     const PartLayout L = part_layout(n, P);
     if (!d_ws || !aligned(d_ws, kAlign))
         return fail(MDX_ERR_INVALID, "mdx_hash_partition: workspace null or not 256-byte aligned");
@@ -228,6 +245,77 @@ int32_t mdx_hash_partition(const void *d_keys, const int64_t *d_payload, int64_t
         return fail(MDX_ERR_WORKSPACE, "mdx_hash_partition: workspace needs " +
                                            std::to_string(L.bytes) + " bytes");
     const PartArgs t = {d_keys, d_payload, n, d_keys_out, d_payload_out, d_offsets, nullptr, d_ws};
+    hipError_t e = launch_partition(&t, 1, key_type, P, 0, 0, 0, stream);
+    return e == hipSuccess ? MDX_OK : hip_fail(e, W);
+}
+
+}  // extern "C"
+
+// ---- partition without allocation ---------------------------------------------------
+// For callers that cannot allocate: the partition's workspace (per-(destination,
+// tile) counts, destination totals; every entry is written before it is read, so
+// nothing needs clearing) lives in this file-scope device array.  Every GPU the
+// library runs on holds its own copy, at its own address, until the process
+// ends.  In host code `scratch` names a host-side stand-in, not device memory:
+// its device address comes from hipGetSymbolAddress, taken once per device with
+// that device current, and only that address is passed to kernels.
+namespace {
+
+static __device__ __align__(256) unsigned char scratch[MDX_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices];
+
+// Device address of the current device's scratch array (looked up on the first
+// call on that device).
+int32_t scratch_address(void **out, const char *W)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_fail(e, W);
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(MDX_ERR_INVALID, std::string(W) + ": device index beyond 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return hip_fail(e, W);
+        if (!p)
+            return fail(MDX_ERR_HIP, std::string(W) + ": scratch array has no device address");
+        g_scratch_addr[dev] = p;
+    }
+    *out = g_scratch_addr[dev];
+    return MDX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t mdx_hash_partition_noalloc(const void *d_keys, const int64_t *d_payload, int64_t n,
+                                   int32_t key_type, int32_t P, void *d_keys_out,
+                                   int64_t *d_payload_out, int64_t *d_offsets,
+                                   hipStream_t stream)
+{
+    g_err.clear();
+    const char *W = "mdx_hash_partition_noalloc";
+    if (int32_t e = check_partition(d_keys, d_payload, n, key_type, P, d_keys_out, d_payload_out,
+                                    d_offsets, W))
+        return e;
+    const PartLayout L = part_layout(n, P);
+    if (L.bytes > (size_t)MDX_NOALLOC_SCRATCH_BYTES)
+        return fail(MDX_ERR_WORKSPACE,
+                    std::string(W) + ": needs " + std::to_string(L.bytes) +
+                        " bytes of scratch, more than the library's " +
+                        std::to_string((size_t)MDX_NOALLOC_SCRATCH_BYTES) +
+                        "; call mdx_hash_partition with a workspace instead");
+    void *ws = nullptr;
+    if (int32_t e = scratch_address(&ws, W))
+        return e;
+    const PartArgs t = {d_keys, d_payload, n, d_keys_out, d_payload_out, d_offsets, nullptr, ws};
     hipError_t e = launch_partition(&t, 1, key_type, P, 0, 0, 0, stream);
     return e == hipSuccess ? MDX_OK : hip_fail(e, W);
 }

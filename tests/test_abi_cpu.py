@@ -269,3 +269,25 @@ def test_transpose_sum_validation():
     assert L._tsum(None, None, 0, None) == mdx.MDX_OK               # n = 0: nothing to do
     m = re.search(r"#define\s+MDX_MAX_TRANSPOSE_N\s+\(INT64_C\(1\)\s*<<\s*(\d+)\)", _header())
     assert m and L.MDX_MAX_TRANSPOSE_N == 1 << int(m.group(1))
+
+
+def test_noalloc_partition_rejects_sizes_beyond_its_scratch():
+    """mdx_hash_partition_noalloc checks its workspace need against the
+    library's scratch array on the host and enqueues nothing when it does
+    not fit (n = 1E8 fits P = 85, not P = 86)."""
+    h = _header()
+    m = re.search(r"#define\s+MDX_NOALLOC_SCRATCH_BYTES\s+\((\d+)u\s*<<\s*(\d+)\)", h)
+    assert m and int(m.group(1)) << int(m.group(2)) == L.MDX_NOALLOC_SCRATCH_BYTES
+    n = 100_000_000
+    k, v, ko, vo, off = (FAKE + i * (1 << 32) for i in range(5))
+    for P in (86, 128, 4096):
+        need = mdx.mdx_hash_partition_workspace_bytes(n, P)
+        assert need > L.MDX_NOALLOC_SCRATCH_BYTES
+        st = L._part_noalloc(k, v, n, mdx.MDX_KEY_I64, P, ko, vo, off, None)
+        assert st == mdx.MDX_ERR_WORKSPACE
+        assert "scratch" in mdx.last_error()
+    assert mdx.mdx_hash_partition_workspace_bytes(n, 85) <= L.MDX_NOALLOC_SCRATCH_BYTES
+    # the usual argument checks come first
+    assert L._part_noalloc(None, v, n, mdx.MDX_KEY_I64, 32, ko, vo, off, None) == mdx.MDX_ERR_INVALID
+    assert L._part_noalloc(k, v, n, mdx.MDX_KEY_I64, 0, ko, vo, off, None) == mdx.MDX_ERR_INVALID
+    assert L._part_noalloc(k, v, n, mdx.MDX_KEY_I64, 32, k, vo, off, None) == mdx.MDX_ERR_INVALID
