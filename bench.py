@@ -35,7 +35,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="paper", choices=["paper", "plain", "batched", "serving", "transpose"])
+    ap.add_argument("--config", default="paper",
+                    choices=["paper", "plain", "skewed", "batched", "serving", "transpose"])
     ap.add_argument("--batch-count", type=int, default=4096,
                     help="batched: number of merges (4096 = the full batch)")
     ap.add_argument("--lanes", type=int, default=4, help="batched: concurrent lanes")
@@ -45,9 +46,11 @@ def parse():
     ap.add_argument("--budget-gb", type=float, default=200.0, help="serving: HBM budget")
     ap.add_argument("--graph-merges", type=int, default=256,
                     help="batched: merges captured per HIP graph (graphs replay in order)")
-    ap.add_argument("--cpu-baseline", default="on", choices=["on", "off"])
+    ap.add_argument("--cpu-baseline", default="on", choices=["on", "off", "full"],
+                    help="on: one-thread oracle on a 0.2-scale sample + all-cores oracle at "
+                         "full size; full: both at full size (the one-thread leg takes ~1 min)")
     ap.add_argument("--cpu-sample-scale", type=float, default=0.2,
-                    help="fraction of the workload the oracle runs on the host")
+                    help="fraction of the workload the one-thread oracle runs on the host")
     return ap.parse_args()
 
 
@@ -65,50 +68,92 @@ def counted_traffic(kernel, workload, sources):
     return None, None
 
 
-def algorithmic_bytes_per_step(kernel, nl, nr, key_bytes, total_out):
-    """Bytes the method itself moves in the given kernel per step (overheads
-    such as the histogram pre-read, table clearing and extra probes are not
-    credited).  Partition: read and write key + payload of every row.  Build:
-    read a left row, write its 16-byte slot.  Probe: read a right row and
-    one 16-byte slot, write 3 x 8 bytes per output row."""
+def step_algorithmic_bytes(nl, nr, key_bytes, total_out):
+    """Bytes one merge moves by the method's own accounting: partition (read
+    and write key + payload of every row of both tables), build (read a left
+    row, write its 16-byte table entry), probe (read a right row and one
+    16-byte table entry), output (key + two payloads per row).  A join whose
+    tables live in LDS moves the table entries on chip, so its HBM minimum is
+    the same less 16 B per input row (algorithmic_hbm_bytes)."""
+    row = key_bytes + 8
+    return (nl + nr) * 2 * row + (nl + nr) * (row + 16) + total_out * (key_bytes + 16)
+
+
+def credited_bytes(kernel, nl, nr, key_bytes, total_out):
+    """HBM bytes of the method credited to one kernel (per merge): the
+    partition scatter reads and writes every row of both tables; the join's
+    emit reads every build and probe row and writes the output.  Histogram
+    pre-reads, the second partition pass and the count's key read are this
+    implementation's overheads and are credited nothing."""
     row = key_bytes + 8
     if kernel == "part_scatter":
         return (nl + nr) * 2 * row
     if kernel == "rj_join":
-        # build: read a left row, write it to the table; probe: read a right
-        # row and one table entry; output rows
-        return nl * (row + 16) + nr * (row + 16) + total_out * (key_bytes + 16)
-    if kernel == "tbl_insert":
-        return nl * (row + 16)
-    if kernel == "probe_chain":
-        return nr * (row + 16) + total_out * (key_bytes + 16)
+        return (nl + nr) * row + total_out * (key_bytes + 16)
     return 0
 
 
-def cpu_baseline(scale):
-    import numpy as np  # noqa: F401
+def host_info():
+    """Host cores this process may use, and the CPU model."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cores_available": avail, "cpu_model": model}
 
+
+def cpu_baselines(mode, scale, full_tables, P):
+    """The oracle timed on the host: (1) one thread, the plain oracle
+    (stable counting-sort partition of both tables + sort-merge join) on a
+    sample of the same generator -- or at full size with mode "full"; (2) the
+    same algorithms over all available host cores (per-thread histograms
+    with a (destination, block)-major prefix, then one destination per
+    thread joined by sort-merge) at full size.  Capped at 16 threads: the
+    GPU machine gives one GPU's process 16 cores."""
     import oracle
     from workloads import config_inputs
 
-    kl, vl, kr, vr = config_inputs("paper", scale=scale)
-    n = kl.size + kr.size
-    log(f"cpu baseline: oracle on {kl.size} x {kr.size} rows (single thread)")
+    info = host_info()
+    if mode == "full":
+        kl, vl, kr, vr = full_tables
+        sample = "the full workload"
+    else:
+        kl, vl, kr, vr = config_inputs("paper", scale=scale)
+        sample = f"the same generator at {scale:g} scale"
+    log(f"cpu baseline: oracle on {kl.size} x {kr.size} rows (one thread)")
     t0 = time.perf_counter()
-    oracle.hash_partition(kl, vl, 32)
-    oracle.hash_partition(kr, vr, 32)
+    oracle.hash_partition(kl, vl, P)
+    oracle.hash_partition(kr, vr, P)
     res = oracle.join(kl, vl, kr, vr)
+    dt1 = time.perf_counter() - t0
+    log(f"cpu baseline: {dt1:.2f} s, |J| = {res['total']}")
+    one = {"value": (kl.size + kr.size) / dt1, "unit": "input rows/s", "cores": 1,
+           "kind": "oracle", **info,
+           "sample": f"{sample}: {kl.size} x {kr.size} rows, P={P}; stable counting-sort "
+                     f"partition of both tables + sort-merge join, {dt1:.2f} s on one host thread"}
+    del kl, vl, kr, vr, res
+    kl, vl, kr, vr = full_tables
+    threads = max(1, min(16, info["cores_available"]))
+    log(f"cpu baseline: threaded oracle on {kl.size} x {kr.size} rows, {threads} threads")
+    t0 = time.perf_counter()
+    r = oracle.merge_threads(kl, vl, kr, vr, P, threads)
     dt = time.perf_counter() - t0
-    log(f"cpu baseline: {dt:.2f} s, |J| = {res['total']}")
-    return {
-        "value": n / dt,
-        "unit": "input rows/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": f"same generator at {scale:g} scale: {kl.size} x {kr.size} rows, P=32; "
-                  f"stable counting-sort partition of both tables + sort-merge join, "
-                  f"{dt:.2f} s on one host thread",
-    }
+    log(f"cpu baseline: {dt:.2f} s, |J| = {r['total']}")
+    allc = {"value": (kl.size + kr.size) / dt, "unit": "input rows/s", "cores": threads,
+            "kind": "oracle (threaded)", **info,
+            "sample": f"the full workload: {kl.size} x {kr.size} rows, P={P}; the partition "
+                      f"(per-thread histograms, stable) and one destination per thread joined "
+                      f"by sort-merge, {dt:.2f} s on {threads} host threads"}
+    return one, allc
 
 
 def copy_ceiling(torch, dev, n=1 << 27, reps=5):
@@ -524,7 +569,8 @@ def main():
     dev = torch.device("cuda:0")
     tk = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
     lk, lv, rk, rv = tk(kl), tk(vl), tk(kr), tk(vr)
-    del kl, vl
+    full_tables = (kl, vl, kr, vr) if args.cpu_baseline != "off" else None
+    del kl, vl, kr, vr
     cap = nr if args.config == "paper" else 4 * nr
     ws = torch.empty(mdx.mdx_merge_workspace_bytes(nl, nr, P, key_bytes), dtype=torch.uint8, device=dev)
     out = (torch.empty(cap, dtype=lk.dtype, device=dev), torch.empty(cap, dtype=torch.int64, device=dev),
@@ -548,42 +594,21 @@ def main():
     st = int(status.item())
     if st != 0 or total > cap:
         raise SystemExit(f"merge failed: status={st} total={total} cap={cap}")
-    if args.config == "paper" and total != round(spec.frac * nr):
-        raise SystemExit(f"unexpected output size {total}")
+    if args.config == "paper":
+        # the closed form of this workload: left keys are distinct, so every
+        # matching right row has exactly one partner
+        ok, ol, orr = (t[:total] for t in out)
+        if total != round(spec.frac * nr) or not torch.equal(ok, lk[ol]) \
+                or not torch.equal(ok, rk[orr]) \
+                or not torch.equal(torch.sort(orr).values, torch.nonzero(rk < nl).flatten()):
+            raise SystemExit(f"merge output differs from the workload's closed form ({total} rows)")
+        del ok, ol, orr
     log(f"output rows {total}")
 
-    # Breakdown pass (not the timed region): every traceable kernel bracketed
-    # by events, to find the dominant one.
-    per_step_launches = 4 + 6 * P
-    prof_steps = 2
-    traces = {k: mdx.KernelTrace(k, prof_steps * per_step_launches) for k in mdx.TRACEABLE_KERNELS}
-    for t in traces.values():
-        t.start()
-    for _ in range(prof_steps):
-        step()
-    torch.cuda.synchronize()
-    mdx.KernelTrace.stop_all()
-    kernels = {}
-    for name, t in traces.items():
-        d = t.durations_ms()
-        if d:
-            kernels[name] = {"ms_per_step": sum(d) / prof_steps,
-                             "launches_per_step": t.launches() / prof_steps,
-                             "avg_launch_ms": sum(d) / len(d)}
-        t.close()
-    for name, k in sorted(kernels.items(), key=lambda kv: -kv[1]["ms_per_step"]):
-        log(f"  {name:13s} {k['ms_per_step']:.3f} ms/step  {k['launches_per_step']:.0f} launches  "
-            f"{k['avg_launch_ms'] * 1e3:.1f} us/launch")
-    credited = {k: v for k, v in kernels.items()
-                if algorithmic_bytes_per_step(k, nl, nr, key_bytes, total) > 0}
-    dom = max(credited, key=lambda k: credited[k]["ms_per_step"])
-
-    # Timed region: K steps; only the dominant kernel is bracketed by events.
-    dtrace = mdx.KernelTrace(dom, args.steps * per_step_launches)
-    dtrace.start()
+    # Timed region: K steps, nothing but the merges between the events.
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    log(f"timing {args.steps} steps (dominant kernel {dom})")
+    log(f"timing {args.steps} steps")
     w0 = time.perf_counter()
     e0.record(stream)
     for _ in range(args.steps):
@@ -591,23 +616,64 @@ def main():
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
-    mdx.KernelTrace.stop_all()
     ms = e0.elapsed_time(e1) / args.steps
     value = (nl + nr) / (ms / 1e3)
     log(f"{ms:.3f} ms/step (wall {wall / args.steps * 1e3:.3f} ms/step), {value:.4g} input rows/s")
-    d = dtrace.durations_ms()
-    kd = {"launches_per_step": dtrace.launches() / args.steps, "avg_launch_ms": sum(d) / len(d)}
-    dtrace.close()
-    bytes_per_launch = algorithmic_bytes_per_step(dom, nl, nr, key_bytes, total) / kd["launches_per_step"]
-    achieved = bytes_per_launch / (kd["avg_launch_ms"] / 1e3) / 1e9
+
+    # Kernel breakdown (separate steps): every traceable kernel bracketed by
+    # HIP events on the stream it runs on -- the per-launch times a rocprofv3
+    # kernel trace of this command reports.
+    per_step_launches = 4 + 6 * P
+    prof_steps = max(2, min(args.steps, 5))
+    traces = {k: mdx.KernelTrace(k, prof_steps * per_step_launches) for k in mdx.TRACEABLE_KERNELS}
+    for t in traces.values():
+        t.start()
+    for _ in range(prof_steps):
+        step()
+    torch.cuda.synchronize()
+    mdx.KernelTrace.stop_all()
     sources = kernel_sources_hash()
-    traffic, traffic_src = counted_traffic(dom, args.config, sources)
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "traffic_source": traffic_src, "bytes_per_launch": int(bytes_per_launch),
-                "avg_launch_us": round(kd["avg_launch_ms"] * 1e3, 2)}
-    step_bytes = (nl + nr) * 2 * (key_bytes + 8) + (nl + nr) * (key_bytes + 8 + 16) \
-        + total * (key_bytes + 16)
+    kernels = {}
+    for name, t in traces.items():
+        d = t.durations_ms()
+        if d:
+            avg_s = sum(d) / len(d) / 1e3
+            launches = t.launches() / prof_steps
+            cb = credited_bytes(name, nl, nr, key_bytes, total) / launches
+            counted, _ = counted_traffic(name, args.config, sources)
+            kernels[name] = {
+                "ms_per_step": round(sum(d) / prof_steps, 4),
+                "launches_per_step": launches,
+                "avg_launch_us": round(avg_s * 1e6, 2),
+                "credited_bytes_per_launch": int(cb),
+                "credited_frac": round(cb / avg_s / 1e9 / HBM_PEAK_GBS, 4) if cb else None,
+                "counted_bytes_per_launch": counted,
+                "counted_frac": round(counted / avg_s / 1e9 / HBM_PEAK_GBS, 4) if counted else None,
+            }
+        t.close()
+    for name, k in sorted(kernels.items(), key=lambda kv: -kv[1]["ms_per_step"]):
+        log(f"  {name:13s} {k['ms_per_step']:.3f} ms/step  {k['launches_per_step']:.0f} launches  "
+            f"{k['avg_launch_us']:.1f} us/launch")
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+
+    alg = step_algorithmic_bytes(nl, nr, key_bytes, total)
+    alg_hbm = alg - (nl + nr) * 16
+    achieved = alg / (ms / 1e3) / 1e9
+    big = [k for k in kernels if kernels[k]["ms_per_step"] >= 0.02]
+    counted_step = [kernels[k]["counted_bytes_per_launch"] for k in big]
+    traffic = int(sum(counted_step)) if counted_step and all(counted_step) else None
+    roofline = {
+        "bound": "hbm",
+        "scope": "one merge: every kernel of the step (partition of both tables, sub-bucket "
+                 "split, join count and emit)",
+        "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": traffic,
+        "algorithmic_bytes": int(alg),
+        "algorithmic_hbm_bytes": int(alg_hbm),
+        "frac_of_hbm_minimum": round(alg_hbm / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "dominant_kernel": {"name": dom, **kernels[dom]},
+    }
     line = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -625,14 +691,17 @@ def main():
                                f"{nl} x {nr} rows, int{8 * key_bytes} key + int64 payload, P={P}",
                    "n_left": nl, "n_right": nr, "P": P, "output_rows": total},
         "roofline": roofline,
-        "step_hbm_fraction": round(step_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "copy_ceiling": copy,
-        "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in kernels.items()},
+        "kernels": kernels,
         "kernel_sources": sources,
     }
-    if args.cpu_baseline == "on":
+    if args.config == "plain":
+        line["us_per_merge"] = round(ms * 1e3, 2)
+    if full_tables is not None:
         del lk, lv, rk, rv, ws, out
-        line["cpu_baseline"] = cpu_baseline(args.cpu_sample_scale)
+        one, allc = cpu_baselines(args.cpu_baseline, args.cpu_sample_scale, full_tables, P)
+        line["cpu_baseline"] = one
+        line["cpu_baseline_all_cores"] = allc
     print(json.dumps(line), flush=True)
 
 

@@ -167,7 +167,8 @@ int32_t mdx_trace_kernel(const char *kernel, hipEvent_t *h_starts, hipEvent_t *h
     }
     static const char *known[] = {"part_hist", "part_scatter", "tbl_init",
                                   "tbl_insert", "probe_chain", "probe_expand",
-                                  "seg_hist", "seg_scatter", "rj_join", "transpose_sum"};
+                                  "seg_hist", "seg_scatter", "rj_join",
+                                  "transpose_sum"};
     bool ok = false;
     for (const char *k : known)
         ok |= std::string(k) == kernel;
@@ -508,7 +509,7 @@ struct MergePlan {
 MergePlan merge_plan(int64_t nL, int64_t nR, int32_t P)
 {
     MergePlan m;
-    const double per = 0.8 * kJoinCap;
+    const double per = kJoinFill * kJoinCap;
     const double want = (double)std::max(nL, nR) / ((double)P * per);
     m.qbits = want <= 1.0 ? 0 : ceil_log2((int64_t)(want + 0.999999));
     // keep the sub-bucket count bounded; oversized sub-buckets fall back to

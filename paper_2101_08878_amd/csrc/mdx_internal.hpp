@@ -170,6 +170,9 @@ constexpr int kJoinCap = 7680;    // build rows per LDS table
 constexpr int kJoinHeads = 4096;  // chain heads per LDS table
 constexpr int kJoinRows = 16;     // probe rows per thread per batch
 constexpr int kJoinBatch = kJoinThreads * kJoinRows;
+// Sub-buckets are sized for this fraction of a table on average (the larger
+// side's rows): the largest of thousands stays far below the cap.
+constexpr double kJoinFill = 0.8;
 
 // One chained-scan tile per sub-bucket.
 struct RJoinLayout {

@@ -218,7 +218,7 @@ __global__ __launch_bounds__(kBlock) void part_offsets(const int64_t *totals0, i
 
 // LDS carve-up of part_scatter (bytes, 16-byte aligned pieces).
 struct ScatterLds {
-    size_t stage_v, stage_k, stage_p, whist, tstart, gbase, scratch, total;
+    size_t stage_v, stage_k, stage_p, stage_d, whist, tstart, gbase, scratch, total;
 };
 
 __host__ __device__ inline size_t al16(size_t x)
@@ -226,7 +226,8 @@ __host__ __device__ inline size_t al16(size_t x)
     return (x + 15) & ~(size_t)15;
 }
 
-__host__ __device__ inline ScatterLds scatter_lds(int T, int P, int key_bytes)
+// dig: the tile also stages every row's next-pass digit byte.
+__host__ __device__ inline ScatterLds scatter_lds(int T, int P, int key_bytes, bool dig)
 {
     ScatterLds L;
     size_t o = 0;
@@ -236,6 +237,8 @@ __host__ __device__ inline ScatterLds scatter_lds(int T, int P, int key_bytes)
     o = al16(o + (size_t)T * key_bytes);
     L.stage_p = o;
     o = al16(o + (size_t)T * 2);
+    L.stage_d = o;  // next-pass digit bytes (when they are written)
+    o = al16(o + (dig ? (size_t)T : 0));
     L.whist = o;  // 16-bit counts: a tile holds at most 4096 rows
     o = al16(o + (size_t)kWavesPerBlock * P * 2);
     L.tstart = o;
@@ -265,24 +268,28 @@ __device__ inline void lds_excl_scan_u32(uint32_t *a, int P, int64_t *scratch)
 }
 
 // Stable scatter of one tile, rows [row0, row_end) (at most kBlock R of them).
-// dfn(h) gives a row's destination in [0, D); base_of(d) the output position
-// of the tile's first row with destination d.  Wave w owns the contiguous
-// rows [row0 + 64 R w, row0 + 64 R (w+1)); step c reads 64 consecutive rows.
-template <typename K, int R, typename DestFn, typename BaseFn>
+// A row's destination in [0, D) is dfn(fmix64(key)); with DIG_OUT every
+// output row's next-pass digit digit_of(h, dshift, dbits) is written beside
+// it (from the same hash).  base_of(d) is the output position of the tile's
+// first row with destination d.  Wave w owns the contiguous rows
+// [row0 + 64 R w, row0 + 64 R (w+1)); step c reads 64 consecutive rows.
+// (The second pass hashes its keys again rather than reading the digit
+// bytes: byte loads, 64 bytes per wave instruction, slowed it by a quarter.)
+template <typename K, int R, bool DIG_OUT, typename DestFn, typename BaseFn>
 __device__ __forceinline__ void scatter_tile(const K *__restrict__ keys,
                                              const int64_t *__restrict__ pay, int64_t row0,
                                              int64_t row_end, int D, int nbits, DestFn dfn,
                                              BaseFn base_of, K *__restrict__ keys_out,
                                              int64_t *__restrict__ pay_out, unsigned char *smem,
-                                             uint8_t *__restrict__ dig_out = nullptr,
-                                             int dshift = 0, int dbits = 0)
+                                             uint8_t *__restrict__ dig_out, int dshift, int dbits)
 {
     constexpr int T = kBlock * R;
     static_assert(T <= 65535, "per-wave tile counts are 16-bit");
-    const ScatterLds L = scatter_lds(T, D, (int)sizeof(K));
+    const ScatterLds L = scatter_lds(T, D, (int)sizeof(K), DIG_OUT);
     int64_t *stage_v = (int64_t *)(smem + L.stage_v);
     K *stage_k = (K *)(smem + L.stage_k);
     uint16_t *stage_p = (uint16_t *)(smem + L.stage_p);
+    uint8_t *stage_d = (uint8_t *)(smem + L.stage_d);
     uint16_t *whist = (uint16_t *)(smem + L.whist);
     uint32_t *tstart = (uint32_t *)(smem + L.tstart);
     int64_t *gbase = (int64_t *)(smem + L.gbase);
@@ -315,11 +322,15 @@ __device__ __forceinline__ void scatter_tile(const K *__restrict__ keys,
     // Rank every row among the earlier rows of its wave with its destination.
     uint16_t *wh = whist + w * D;
     uint32_t pr[R], rk[R];
+    uint8_t dg[R];
 #pragma unroll
     for (int c = 0; c < R; ++c) {
         const int64_t r = wrow0 + (int64_t)c * kWave + lane;
         const bool valid = r < row_end;
-        const uint32_t p = valid ? dfn(fmix64(key_bits(kr[c]))) : 0u;
+        const uint64_t h = fmix64(key_bits(kr[c]));
+        const uint32_t p = valid ? dfn(h) : 0u;
+        if (DIG_OUT)
+            dg[c] = (uint8_t)digit_of(h, dshift, dbits);
         uint64_t m = ballot(valid);
         for (int b = 0; b < nbits; ++b) {
             const bool bit = (p >> b) & 1u;
@@ -365,6 +376,8 @@ __device__ __forceinline__ void scatter_tile(const K *__restrict__ keys,
             stage_k[s] = kr[c];
             stage_v[s] = vr[c];
             stage_p[s] = (uint16_t)pr[c];
+            if (DIG_OUT)
+                stage_d[s] = dg[c];
         }
     }
     __syncthreads();
@@ -380,12 +393,12 @@ __device__ __forceinline__ void scatter_tile(const K *__restrict__ keys,
         // bytes written, 26% slower at a fan-out of 128.
         keys_out[dst] = stage_k[s];
         pay_out[dst] = stage_v[s];
-        if (dig_out)
-            dig_out[dst] = (uint8_t)digit_of(fmix64(key_bits(stage_k[s])), dshift, dbits);
+        if (DIG_OUT)
+            dig_out[dst] = stage_d[s];
     }
 }
 
-template <typename K, int R>
+template <typename K, int R, bool DIG>
 __global__ __launch_bounds__(kBlock) void part_scatter(PartPair<K> T, Dest d, int dshift, int dbits)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -393,7 +406,7 @@ __global__ __launch_bounds__(kBlock) void part_scatter(PartPair<K> T, Dest d, in
     const bool second = g >= T.t[0].ntiles;
     const PartTable<K> tb = pick(T, second);
     const int64_t tile = second ? g - T.t[0].ntiles : g;
-    scatter_tile<K, R>(
+    scatter_tile<K, R, DIG>(
         tb.keys, tb.pay, tile * (int64_t)(kBlock * R), tb.n, d.ndest, d.nbits,
         [&](uint64_t h) { return dest_of(h, d); },
         [&](int p) { return tb.off[p] + tb.cnt[(int64_t)p * tb.ntiles + tile]; }, tb.keys_out,
@@ -605,14 +618,14 @@ __global__ __launch_bounds__(kBlock) void seg_scatter(SegPair<K> T, int nseg, in
     const int64_t chunk = tb.chunk_start[a] + lt / kSegChunkTiles;
     const int64_t r0 = tb.segoff[a] + lt * kSegTile;
     const int64_t r1 = r0 + kSegTile < tb.segoff[a + 1] ? r0 + kSegTile : tb.segoff[a + 1];
-    scatter_tile<K, kSegRows>(
+    scatter_tile<K, kSegRows, false>(
         tb.keys, tb.pay, r0, r1, D, bits,
         [&](uint64_t h) { return digit_of(h, shift, bits); },
         [&](int q) {
             return tb.outoff[(int64_t)a * D + q] + tb.csum[chunk * D + q] +
                    (int64_t)tb.cnt[t * D + q];
         },
-        tb.keys_out, tb.pay_out, smem);
+        tb.keys_out, tb.pay_out, smem, nullptr, 0, 0);
 }
 
 template <typename K, int R>
@@ -650,16 +663,23 @@ hipError_t run_partition(const PartArgs *tables, int ntables, int32_t P, int sbi
     hipLaunchKernelGGL(part_offsets, dim3((unsigned)ntables), dim3(kBlock), 0, s, T.t[0].totals,
                        T.t[0].off, T.t[1].totals, T.t[1].off, D);
     if (tiles > 0) {
-        const size_t lds = scatter_lds(kBlock * R, D, (int)sizeof(K)).total;
+        // digit bytes are written for both tables or for neither
+        const bool dig = T.t[0].dig != nullptr;
+        const size_t lds = scatter_lds(kBlock * R, D, (int)sizeof(K), dig).total;
         if (lds > kMaxLdsBytes)
             return hipErrorInvalidValue;  // cannot happen for D <= MDX_MAX_P
-        hipError_t e = hipFuncSetAttribute((const void *)part_scatter<K, R>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        const void *fn = dig ? (const void *)part_scatter<K, R, true>
+                             : (const void *)part_scatter<K, R, false>;
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess)
             return e;
         trace_begin("part_scatter", s);
-        hipLaunchKernelGGL((part_scatter<K, R>), dim3((unsigned)tiles), dim3(kBlock), lds, s, T,
-                           d, dshift, dbits);
+        if (dig)
+            hipLaunchKernelGGL((part_scatter<K, R, true>), dim3((unsigned)tiles), dim3(kBlock), lds,
+                               s, T, d, dshift, dbits);
+        else
+            hipLaunchKernelGGL((part_scatter<K, R, false>), dim3((unsigned)tiles), dim3(kBlock),
+                               lds, s, T, d, dshift, dbits);
         trace_end("part_scatter", s);
     }
     return hipGetLastError();
@@ -692,7 +712,7 @@ hipError_t run_seg_partition(const SegArgs *tables, int ntables, int64_t nseg, i
         t.max_chunks = L.max_chunks;
     }
     const int ns = (int)nseg;
-    const size_t lds = scatter_lds(kSegTile, 1 << bits, (int)sizeof(K)).total;
+    const size_t lds = scatter_lds(kSegTile, 1 << bits, (int)sizeof(K), false).total;
     if (lds > kMaxLdsBytes)
         return hipErrorInvalidValue;  // cannot happen for bits <= 8
     hipLaunchKernelGGL(seg_plan<K>, dim3((unsigned)ntables), dim3(kBlock), 0, s, T, ns);

@@ -5,10 +5,9 @@
 // Both sides arrive split into sub-buckets (partition p, top hash bits q), so
 // that a sub-bucket's build rows fit one workgroup's LDS.  A workgroup takes
 // sub-buckets in order from a ticket counter; for each it
-//   1. loads the build rows into LDS: full 64-bit hash, payload, and a chain
-//      link; bucket heads hold the last row inserted per bucket (LDS atomic
-//      exchange), so equal keys share a chain and repeated keys need nothing
-//      special (fmix64 is a bijection: equal hashes are equal keys);
+//   1. loads the build rows into LDS: key, payload, and a chain link; bucket
+//      heads hold the last row inserted per bucket (LDS atomic exchange), so
+//      equal keys share a chain and repeated keys need nothing special;
 //   2. counts the output rows of all its probe rows (walking each row's
 //      chain), publishes that count to a chained scan over sub-buckets
 //      (decoupled look-back), and receives the output rows of all earlier
@@ -18,7 +17,11 @@
 //      otherwise they are read and looked up again.
 // Sub-buckets are numbered partition-major, so partition p's output is the
 // contiguous range [out_off[p], out_off[p+1]).  Global memory is only
-// streamed: the random accesses of the join all hit LDS.
+// streamed: the random accesses of the join all hit LDS.  The partition
+// already sent each key to its sub-bucket by fmix64, so inside a sub-bucket a
+// key's chain is chosen by a one-multiply hash of the key itself and keys are
+// compared directly: fmix64 (six 32-bit multiplies, quarter-rate
+// instructions) is not computed again here.
 //
 // Latency hiding with one workgroup per CU: the first probe batch is loaded
 // while the build rows are inserted, and the hash chains of a thread's probe
@@ -42,18 +45,24 @@ constexpr int kCellsPerLane = kCells / kWave;
 static_assert(kCells % kWave == 0, "one wave scans the partial sums");
 static_assert(kSent <= 0xffffu, "chain links are 16-bit");
 constexpr int kWalk = 4;  // probe rows whose chains are walked together
-// Phase boundaries of a sub-bucket (0 ticket, 1 build, 2 count, 3 chained
-// scan, 4 emit); a timing build defines MDX_PHASE to record them.
-#ifndef MDX_PHASE
-#define MDX_PHASE(k)
-#endif
 static_assert(kJoinRows % kWalk == 0, "walk groups tile the thread's rows");
 
-// Chain bucket: hash bits 20..31, away from the partition's low bits and the
-// sub-bucket's top bits.
-__device__ __forceinline__ uint32_t bucket_of(uint64_t h)
+// Chain of a key inside its sub-bucket: multiplicative (Fibonacci) hashing
+// of the key's two 32-bit halves folded together.
+__device__ __forceinline__ uint32_t bucket_of(int64_t key)
 {
-    return (uint32_t)(h >> 20) & (kJoinHeads - 1);
+    static_assert((kJoinHeads & (kJoinHeads - 1)) == 0, "power-of-two heads");
+    constexpr int kLog = __builtin_ctz(kJoinHeads);
+    const uint32_t x = (uint32_t)key ^ (uint32_t)((uint64_t)key >> 32);
+    return (x * 0x9E3779B1u) >> (32 - kLog);
+}
+
+// Values every lane of the workgroup holds alike, in scalar registers.
+__device__ __forceinline__ int64_t uniform(int64_t x)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)x >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
 __global__ __launch_bounds__(kBlock) void rj_plan(const int64_t *__restrict__ subL, int64_t S,
@@ -112,17 +121,24 @@ __global__ __launch_bounds__(kBlock) void rj_plan_one(const int64_t *__restrict_
 // Sub-buckets up to which rj_plan_one runs.
 constexpr int64_t kPlanOneMax = (int64_t)kBlock * kPlanOnePerThread;
 
-// This thread's rows of the batch starting at rb: rb + j * kJoinThreads + tid.
+// This thread's rows of the batch starting at rb (the same on every lane),
+// up to re (rb < re): rb + j kJoinThreads + tid.  Rows past re load the
+// batch's last row instead (no branch per load) and are ignored by the
+// callers, which check r < re.
 template <typename K>
 __device__ __forceinline__ void load_batch(const K *__restrict__ rk, const int64_t *__restrict__ rv,
                                            int64_t rb, int64_t re, K *kk, int64_t *vv)
 {
-    const int tid = threadIdx.x;
+    const K *kb = rk + rb;
+    const int64_t *vb = rv + rb;
+    const int64_t left = re - rb;
+    const uint32_t last = (uint32_t)((left < kJoinBatch ? left : kJoinBatch) - 1);
 #pragma unroll
     for (int j = 0; j < kJoinRows; ++j) {
-        const int64_t r = rb + (int64_t)j * kJoinThreads + tid;
-        kk[j] = r < re ? __builtin_nontemporal_load(rk + r) : K(0);
-        vv[j] = r < re ? __builtin_nontemporal_load(rv + r) : 0;
+        uint32_t r = (uint32_t)(j * kJoinThreads) + threadIdx.x;
+        r = r < last ? r : last;
+        kk[j] = __builtin_nontemporal_load(kb + r);
+        vv[j] = __builtin_nontemporal_load(vb + r);
     }
 }
 
@@ -132,31 +148,32 @@ __device__ __forceinline__ void load_batch(const K *__restrict__ rk, const int64
 // branches: a finished chain sits on the sentinel row, whose link points to
 // itself, so every step issues all kWalk rows' LDS reads at once.
 template <typename K>
-__device__ __forceinline__ void match_batch(int64_t rb, int64_t re, bool any, const uint64_t *th,
+__device__ __forceinline__ void match_batch(int64_t rb, int64_t re, bool any, const int64_t *tkey,
                                             const uint16_t *tn, const uint32_t *head, const K *kk,
                                             uint32_t *mf)
 {
-    const int tid = threadIdx.x;
+    const int64_t left = re - rb;
+    const uint32_t n = any ? (uint32_t)(left < kJoinBatch ? left : kJoinBatch) : 0u;
 #pragma unroll
     for (int g = 0; g < kJoinRows; g += kWalk) {
-        uint64_t h[kWalk];
+        int64_t h[kWalk];
         uint32_t e[kWalk];
         bool live = false;
 #pragma unroll
         for (int i = 0; i < kWalk; ++i) {
             const int j = g + i;
-            const int64_t r = rb + (int64_t)j * kJoinThreads + tid;
+            const uint32_t r = (uint32_t)(j * kJoinThreads) + threadIdx.x;
             mf[j] = 0;
-            h[i] = fmix64(key_bits(kk[j]));
-            e[i] = (any && r < re) ? head[bucket_of(h[i])] : kSent;
+            h[i] = (int64_t)kk[j];
+            e[i] = r < n ? head[bucket_of(h[i])] : kSent;
             live |= e[i] != kSent;
         }
         while (ballot(live)) {
-            uint64_t x[kWalk];
+            int64_t x[kWalk];
             uint32_t nx[kWalk];
 #pragma unroll
             for (int i = 0; i < kWalk; ++i) {
-                x[i] = th[e[i]];
+                x[i] = tkey[e[i]];
                 nx[i] = tn[e[i]];
             }
             live = false;
@@ -220,7 +237,7 @@ __device__ __forceinline__ int64_t cell_scan(int64_t *cw, int lane)
 // the batch's first match; cw holds the exclusive cell prefixes.
 template <typename K>
 __device__ __forceinline__ void emit_batch(const K *kk, const int64_t *vv, const uint32_t *mf,
-                                           const int64_t *cw, int64_t base, const uint64_t *th,
+                                           const int64_t *cw, int64_t base, const int64_t *tkey,
                                            const int64_t *tp, const uint16_t *tn, K *out_key,
                                            int64_t *out_l, int64_t *out_r, int lane, int wv)
 {
@@ -228,22 +245,27 @@ __device__ __forceinline__ void emit_batch(const K *kk, const int64_t *vv, const
     for (int j = 0; j < kJoinRows; ++j) {
         const uint32_t cnt = mf[j] >> 16, fst = mf[j] & 0xffffu;
         const uint64_t one = ballot(cnt == 1), many = ballot(cnt > 1);
+        if (!(one | many))
+            continue;
         const int64_t before =
             many ? wave_incl_scan((int64_t)cnt, lane) - (int64_t)cnt : (int64_t)mbcnt(one);
-        if (cnt == 0)
-            continue;
-        int64_t at = base + cw[j * kJoinWaves + wv] + before;
+        // the wave's first output row of this step: a scalar base; lanes add
+        // a 32-bit offset (a step of a wave has at most 64 kJoinCap rows)
+        const int64_t wb = uniform(base + cw[j * kJoinWaves + wv]);
+        K *ok = out_key + wb;
+        int64_t *ol = out_l + wb, *orr = out_r + wb;
+        uint32_t at = (uint32_t)before;
         if (cnt == 1) {
-            out_key[at] = kk[j];
-            out_l[at] = tp[fst];
-            out_r[at] = vv[j];
-        } else {
-            const uint64_t h = fmix64(key_bits(kk[j]));
+            ok[at] = kk[j];
+            ol[at] = tp[fst];
+            orr[at] = vv[j];
+        } else if (cnt > 1) {
+            const int64_t h = (int64_t)kk[j];
             for (uint32_t e = fst; e != kSent; e = tn[e]) {
-                if (th[e] == h) {
-                    out_key[at] = kk[j];
-                    out_l[at] = tp[e];
-                    out_r[at] = vv[j];
+                if (tkey[e] == h) {
+                    ok[at] = kk[j];
+                    ol[at] = tp[e];
+                    orr[at] = vv[j];
                     ++at;
                 }
             }
@@ -261,7 +283,7 @@ __attribute__((amdgpu_waves_per_eu(kJoinSimdWaves, kJoinSimdWaves))) void rj_joi
     const K *__restrict__ rk, const int64_t *__restrict__ rv, const int64_t *__restrict__ subR,
     RJoinWs w, ProbeOut o, int32_t *status)
 {
-    __shared__ uint64_t th[kJoinCap + 1];  // hash of build row i
+    __shared__ int64_t tkey[kJoinCap + 1]; // key of build row i
     __shared__ int64_t tp[kJoinCap];       // payload of build row i
     __shared__ uint16_t tn[kJoinCap + 1];  // next row in i's chain
     __shared__ uint32_t head[kJoinHeads];  // last row inserted per bucket
@@ -274,7 +296,7 @@ __attribute__((amdgpu_waves_per_eu(kJoinSimdWaves, kJoinSimdWaves))) void rj_joi
     K *out_key = (K *)o.key;
     const int64_t S = w.S;
     if (tid == 0) {
-        th[kSent] = 0;
+        tkey[kSent] = 0;
         tn[kSent] = (uint16_t)kSent;
     }
 
@@ -285,11 +307,10 @@ __attribute__((amdgpu_waves_per_eu(kJoinSimdWaves, kJoinSimdWaves))) void rj_joi
         if (tid == 0)
             s_next = (int64_t)atomicAdd(w.ticket, 1u);
         __syncthreads();
-        const int64_t s = s_next;
+        const int64_t s = uniform(s_next);
         __syncthreads();  // everyone has read s_next before it is replaced
         if (s >= S)
             break;
-        MDX_PHASE(0);
         const int64_t bL = subL[s], nb = subL[s + 1] - bL;  // nb <= kJoinCap (plan flag)
         const int64_t bR = subR[s], eR = subR[s + 1];
         const int64_t nbatch = (eR - bR + kJoinBatch - 1) / kJoinBatch;
@@ -307,36 +328,40 @@ __attribute__((amdgpu_waves_per_eu(kJoinSimdWaves, kJoinSimdWaves))) void rj_joi
             for (int i = tid; i < kJoinHeads; i += kJoinThreads)
                 head[i] = kSent;
             __syncthreads();
+            // rows past nb load the last build row (no branch per load)
+            const K *kb = lk + bL;
+            const int64_t *vb = lv + bL;
+            const uint32_t last = (uint32_t)nb - 1;
             for (int base = 0; base < (int)nb; base += kBuildBatch * kJoinThreads) {
                 K bk[kBuildBatch];
                 int64_t bv[kBuildBatch];
 #pragma unroll
                 for (int j = 0; j < kBuildBatch; ++j) {
-                    const int i = base + j * kJoinThreads + tid;
-                    bk[j] = i < nb ? __builtin_nontemporal_load(lk + bL + i) : K(0);
-                    bv[j] = i < nb ? __builtin_nontemporal_load(lv + bL + i) : 0;
+                    uint32_t i = (uint32_t)(base + j * kJoinThreads) + tid;
+                    i = i < last ? i : last;
+                    bk[j] = __builtin_nontemporal_load(kb + i);
+                    bv[j] = __builtin_nontemporal_load(vb + i);
                 }
 #pragma unroll
                 for (int j = 0; j < kBuildBatch; ++j) {
                     const int i = base + j * kJoinThreads + tid;
                     if (i < nb) {
-                        const uint64_t h = fmix64(key_bits(bk[j]));
-                        th[i] = h;
+                        const int64_t k = (int64_t)bk[j];
+                        tkey[i] = k;
                         tp[i] = bv[j];
-                        tn[i] = (uint16_t)atomicExch(&head[bucket_of(h)], (uint32_t)i);
+                        tn[i] = (uint16_t)atomicExch(&head[bucket_of(k)], (uint32_t)i);
                     }
                 }
             }
             __syncthreads();
         }
 
-        MDX_PHASE(1);
         // Count every probe row's matches.
         int64_t total = 0;
         for (int64_t b = 0; b < nbatch; ++b) {
             if (b > 0)
                 load_batch(rk, rv, bR + b * kJoinBatch, eR, kk, vv);
-            match_batch(bR + b * kJoinBatch, eR, any, th, tn, head, kk, mf);
+            match_batch(bR + b * kJoinBatch, eR, any, tkey, tn, head, kk, mf);
             cell_sums(mf, cw, lane, wv);
             __syncthreads();
             if (wv == 0) {
@@ -348,7 +373,6 @@ __attribute__((amdgpu_waves_per_eu(kJoinSimdWaves, kJoinSimdWaves))) void rj_joi
             total += s_total;
         }
 
-        MDX_PHASE(2);
         // Chained scan over sub-buckets.
         if (wv == 0) {
             const int64_t ex = lookback(w.status, s, total, lane, status);
@@ -359,7 +383,6 @@ __attribute__((amdgpu_waves_per_eu(kJoinSimdWaves, kJoinSimdWaves))) void rj_joi
         }
         __syncthreads();
         const int64_t E = s_excl;
-        MDX_PHASE(3);
 
         // Write the output rows.
         if (E + total > o.cap) {
@@ -370,12 +393,12 @@ __attribute__((amdgpu_waves_per_eu(kJoinSimdWaves, kJoinSimdWaves))) void rj_joi
                 if (wv == 0)
                     cell_scan(cw, lane);
                 __syncthreads();
-                emit_batch(kk, vv, mf, cw, E, th, tp, tn, out_key, o.lpay, o.rpay, lane, wv);
+                emit_batch(kk, vv, mf, cw, E, tkey, tp, tn, out_key, o.lpay, o.rpay, lane, wv);
             } else {
                 int64_t run = E;
                 for (int64_t b = 0; b < nbatch; ++b) {
                     load_batch(rk, rv, bR + b * kJoinBatch, eR, kk, vv);
-                    match_batch(bR + b * kJoinBatch, eR, any, th, tn, head, kk, mf);
+                    match_batch(bR + b * kJoinBatch, eR, any, tkey, tn, head, kk, mf);
                     cell_sums(mf, cw, lane, wv);
                     __syncthreads();
                     if (wv == 0) {
@@ -384,14 +407,13 @@ __attribute__((amdgpu_waves_per_eu(kJoinSimdWaves, kJoinSimdWaves))) void rj_joi
                             s_total = all;
                     }
                     __syncthreads();
-                    emit_batch(kk, vv, mf, cw, run, th, tp, tn, out_key, o.lpay, o.rpay, lane, wv);
+                    emit_batch(kk, vv, mf, cw, run, tkey, tp, tn, out_key, o.lpay, o.rpay, lane, wv);
                     run += s_total;
                     __syncthreads();  // cw and s_total are reused by the next batch
                 }
             }
         }
         __syncthreads();  // the table is reused by the next sub-bucket
-        MDX_PHASE(4);
     }
 }
 
