@@ -160,15 +160,28 @@ hipError_t launch_seg_partition(const SegArgs *tables, int ntables, int key_byte
 // Sub-bucket s of S = P 2^qbits holds build rows [subL[s], subL[s+1]) and
 // probe rows [subR[s], subR[s+1]); partition p owns sub-buckets
 // [p 2^qbits, (p+1) 2^qbits).
-// One 512-thread workgroup per CU holds a 152 KB table in LDS (of 160 KB).
-// Two half-size workgroups per CU, or one of 1024 threads, measured no
-// faster: the time per sub-bucket is set by the latency of its dependent
-// steps, not by the number of waves.
-constexpr int kJoinPerCu = 1;
+// Two 512-thread workgroups per CU, each with a 76 KB table in LDS: the time
+// of a sub-bucket is mostly the latency of its dependent steps (ticket,
+// offsets, row loads, chained scan), and a second workgroup on the CU runs
+// while the first waits.  (One workgroup with a 152 KB table for twice the
+// rows, and so half the sub-buckets, was 10% slower at 1E8 x 1E8.)
+#ifndef MDX_JOIN_PER_CU
+#define MDX_JOIN_PER_CU 2
+#endif
+#ifndef MDX_JOIN_CAP
+#define MDX_JOIN_CAP 3840
+#endif
+#ifndef MDX_JOIN_HEADS
+#define MDX_JOIN_HEADS 2048
+#endif
+#ifndef MDX_JOIN_ROWS
+#define MDX_JOIN_ROWS 8
+#endif
+constexpr int kJoinPerCu = MDX_JOIN_PER_CU;
 constexpr int kJoinThreads = 512;
-constexpr int kJoinCap = 7680;    // build rows per LDS table
-constexpr int kJoinHeads = 4096;  // chain heads per LDS table
-constexpr int kJoinRows = 16;     // probe rows per thread per batch
+constexpr int kJoinCap = MDX_JOIN_CAP;      // build rows per LDS table
+constexpr int kJoinHeads = MDX_JOIN_HEADS;  // chain heads per LDS table
+constexpr int kJoinRows = MDX_JOIN_ROWS;    // probe rows per thread per batch
 constexpr int kJoinBatch = kJoinThreads * kJoinRows;
 // Sub-buckets are sized for this fraction of a table on average (the larger
 // side's rows): the largest of thousands stays far below the cap.
