@@ -43,6 +43,14 @@ def parse():
     ap.add_argument("--duration", type=float, default=60.0, help="serving: seconds of arrivals")
     ap.add_argument("--rate", type=float, default=2000.0, help="serving: requests per second")
     ap.add_argument("--slots", type=int, default=8, help="serving: concurrent slots")
+    ap.add_argument("--serve-mode", default="merge", choices=["merge", "probe"],
+                    help="serving: requests bring both tables, or probe device-resident tables")
+    ap.add_argument("--serve-unique", type=int, default=256,
+                    help="serving: distinct requests drawn on the device (the stream picks among them)")
+    ap.add_argument("--overload-rate", type=float, default=5000.0,
+                    help="serving: the second point's arrival rate (above FIFO capacity)")
+    ap.add_argument("--overload-duration", type=float, default=10.0,
+                    help="serving: seconds of arrivals at the overload rate")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="serving: HBM budget")
     ap.add_argument("--graph-merges", type=int, default=256,
                     help="batched: merges captured per HIP graph (graphs replay in order)")
@@ -350,113 +358,208 @@ def run_batched(args):
     print(json.dumps(line), flush=True)
 
 
-def serve_run(torch, mdx, reqs, pool, slots, budget, dev, max_rows):
-    """Serve `reqs` (arrival s, nL, nR, pool index) as they arrive; returns
-    (latencies in ms, elapsed s).  A request is admitted when a slot, an
-    output buffer and the memory budget allow, in arrival order."""
+SERVE_MAX_ROWS = 20_000_000
+
+
+def serving_pool(torch, dev, n_unique, seed=0):
+    """The distinct requests of the serving workload, drawn on the device
+    before the timed loop (requests of the stream then pick one each).  One
+    permutation lk of [0, 2E7) gives every left table as a prefix lk[:nL]
+    (distinct keys); request u: nL, nR log-uniform in [1E4, 2E7], match
+    fraction f ~ U[0.1, 0.9]; its right keys: m = round(f nR) drawn uniformly
+    from its own left rows lk[:nL], the other nR - m from [2E7, 4E7) (never a
+    left key), shuffled.  |J| = m exactly.  Payload = row index."""
+    import numpy as np
+    N = SERVE_MAX_ROWS
+    rng = np.random.default_rng(seed)
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed + 17)
+    lk = torch.randperm(N, generator=g, device=dev, dtype=torch.int64)
+    pay = torch.arange(N, dtype=torch.int64, device=dev)
+    reqs = []
+    for u in range(n_unique):
+        nl = int(round(np.exp(rng.uniform(np.log(1e4), np.log(2e7)))))
+        nr = int(round(np.exp(rng.uniform(np.log(1e4), np.log(2e7)))))
+        f = float(rng.uniform(0.1, 0.9))
+        m = int(round(f * nr))
+        hit = lk[torch.randint(0, nl, (m,), generator=g, device=dev)]
+        miss = torch.randint(N, 2 * N, (nr - m,), generator=g, device=dev)
+        rk = torch.cat([hit, miss])[torch.randperm(nr, generator=g, device=dev)].contiguous()
+        reqs.append({"nl": nl, "nr": nr, "f": f, "m": m, "rk": rk})
+    return lk, pay, reqs
+
+
+def serve_run(torch, mdx, stream_reqs, pool, slots, budget, dev, mode, tables=None):
+    """Serve the stream (arrival s, unique request index) as it arrives;
+    returns (latencies in ms, elapsed s, totals, statuses).  A request is
+    admitted in arrival order when a slot, an output buffer and the memory
+    budget allow.  mode "merge": each request brings its left and right
+    table; mode "probe": each request probes a build table kept on the
+    device (tables[t], built once) with its right rows."""
     from collections import deque
 
+    lk, pay, uniq = pool
+    N = SERVE_MAX_ROWS
+    n = len(stream_reqs)
     nbuf = slots + 4
-    bufs = [(torch.empty(max_rows, dtype=torch.int64, device=dev),
-             torch.empty(max_rows, dtype=torch.int64, device=dev),
-             torch.empty(max_rows, dtype=torch.int64, device=dev),
-             torch.empty(9, dtype=torch.int64, device=dev)) for _ in range(nbuf)]
+    bufs = [tuple(torch.empty(N, dtype=torch.int64, device=dev) for _ in range(3))
+            for _ in range(nbuf)]
     free = list(range(nbuf))
-    status = torch.zeros(len(reqs), dtype=torch.int32, device=dev)
-    lat = [0.0] * len(reqs)
+    status = torch.zeros(n, dtype=torch.int32, device=dev)
+    offsets = torch.zeros((n, 9), dtype=torch.int64, device=dev)
+    lat = [0.0] * n
     owner = {}
     queue = deque()
     nxt = done = 0
-    with mdx.Server(slots, max_rows, max_rows, 8, budget, device=dev) as srv:
+    with mdx.Server(slots, N, N, 8, budget, device=dev) as srv:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        while done < len(reqs):
+        while done < n:
             now = time.perf_counter() - t0
-            while nxt < len(reqs) and reqs[nxt][0] <= now:
+            while nxt < n and stream_reqs[nxt][0] <= now:
                 queue.append(nxt)
                 nxt += 1
             while queue and free:
                 i = queue[0]
-                _, nl, nr, k = reqs[i]
+                r = uniq[stream_reqs[i][1]]
                 b = bufs[free[-1]]
-                lk, rk = pool[k]
-                job = mdx.MergeJob(lk[:nl], pool[9][:nl], rk[:nr], pool[9][:nr], 8, nr,
-                                   out=b[:3], out_offsets=b[3], status=status[i:i + 1])
-                if srv.submit(job, i) is None:
+                if mode == "merge":
+                    nl, nr = r["nl"], r["nr"]
+                    job = mdx.MergeJob(lk[:nl], pay[:nl], r["rk"], pay[:nr], 8, r["m"],
+                                       out=b, out_offsets=offsets[i], status=status[i:i + 1])
+                    ok = srv.submit(job, i, ready=0)
+                else:
+                    job = mdx.ProbeJob(tables[r["table"]], r["rk"], pay[:r["nr"]], r["m"],
+                                       out=b, out_offsets=offsets[i], status=status[i:i + 1])
+                    ok = srv.submit_probe(job, i, ready=0)
+                if ok is None:
                     break
                 owner[i] = free.pop()
                 queue.popleft()
             for i in srv.poll():
-                lat[i] = (time.perf_counter() - t0 - reqs[i][0]) * 1e3
+                lat[i] = (time.perf_counter() - t0 - stream_reqs[i][0]) * 1e3
                 free.append(owner.pop(i))
                 done += 1
         elapsed = time.perf_counter() - t0
-    if int(status.max().item()) != 0:
-        raise SystemExit("serving: a merge reported a device status")
-    return lat, elapsed
+    return lat, elapsed, offsets[:, -1].cpu(), status.cpu()
+
+
+def serving_check_rows(torch, mdx, pool, tables, dev):
+    """Every distinct request run alone (not timed), its rows checked: |J| =
+    m, every row's key equals the left key at its left payload and the
+    right key at its right payload, the right payloads are exactly the hit
+    rows (each right row has at most one partner: left keys are distinct)."""
+    lk, pay, uniq = pool
+    bad = 0
+    for u, r in enumerate(uniq):
+        nr, m = r["nr"], r["m"]
+        if tables is None:
+            nl = r["nl"]
+            ok, ol, orr, off = mdx.mdx_merge(lk[:nl], pay[:nl], r["rk"], pay[:nr], 8,
+                                             out_capacity=max(m, 1))
+            left = lk[:nl]
+        else:
+            t = tables[r["table"]]
+            rk, rv, ro = mdx.mdx_hash_partition(r["rk"], pay[:nr], 8)
+            ok, ol, orr, off = mdx.mdx_join_probe(t, rk, rv, ro, out_capacity=max(m, 1))
+            left = lk[:r["nl"]]
+        total = int(off[-1].item())
+        if total != m:
+            bad += 1
+            continue
+        ok, ol, orr = ok[:m], ol[:m], orr[:m]
+        hits = torch.nonzero(r["rk"] < SERVE_MAX_ROWS).flatten()
+        if not (torch.equal(ok, left[ol]) and torch.equal(ok, r["rk"][orr])
+                and torch.equal(torch.sort(orr).values, hits)):
+            bad += 1
+    return bad
 
 
 def run_serving(args):
-    """Serving line: a Poisson stream of merge requests (sizes log-uniform in
-    [1E4, 2E7] rows per side, int64 keys, match fraction uniform in
-    [0.1, 0.9], P=8), admitted as slots and the HBM budget free up, against
-    the plain path (one slot: one merge at a time, in arrival order).
-    Requests read prefixes of device-resident tables drawn beforehand (nine
-    match fractions 0.1 ... 0.9), so no request waits for input generation."""
+    """Serving lines: a Poisson stream of requests (sizes log-uniform in
+    [1E4, 2E7] rows per side, int64 keys, match fraction U[0.1, 0.9] per
+    request, P=8) admitted as slots and the HBM budget free up (continuous
+    batching), against one request at a time in arrival order (FIFO), at the
+    configured rate and at an overload rate.  Mode "merge": each request
+    brings both tables; mode "probe": the build tables stay on the device
+    (built once with mdx_join_build) and each request probes one."""
     import numpy as np
     import torch
 
     import paper_2101_08878_amd as mdx
 
     dev = torch.device("cuda:0")
-    max_rows = 20_000_000
-    g = torch.Generator(device=dev)
-    pool = []
-    for k in range(9):
-        f = 0.1 * (k + 1)
-        g.manual_seed(7_000 + k)
-        lk = torch.randperm(max_rows, generator=g, device=dev, dtype=torch.int64)
-        m = int(round(f * max_rows))
-        hit = lk[torch.randint(0, max_rows, (m,), generator=g, device=dev, dtype=torch.int64)]
-        miss = torch.randint(max_rows, 2 * max_rows, (max_rows - m,), generator=g, device=dev,
-                             dtype=torch.int64)
-        rk = torch.cat([hit, miss])[torch.randperm(max_rows, generator=g, device=dev)].contiguous()
-        pool.append((lk, rk))
-    pool.append(torch.arange(max_rows, dtype=torch.int64, device=dev))  # payloads
-    torch.cuda.synchronize()
-    rng = np.random.default_rng(0)
-    n = int(round(args.rate * args.duration))
-    arrivals = np.cumsum(rng.exponential(1.0 / args.rate, n))
-    reqs = []
-    for i in range(n):
-        nl = int(round(np.exp(rng.uniform(np.log(1e4), np.log(2e7)))))
-        nr = int(round(np.exp(rng.uniform(np.log(1e4), np.log(2e7)))))
-        f = rng.uniform(0.1, 0.9)
-        reqs.append((float(arrivals[i]), nl, nr, int(min(8, max(0, round(f * 10) - 1)))))
-    rows = sum(r[1] + r[2] for r in reqs)
+    n_unique = args.serve_unique
+    log(f"serving: drawing {n_unique} distinct requests on the device")
+    pool = serving_pool(torch, dev, n_unique)
+    lk, pay, uniq = pool
+    tables = None
+    if args.serve_mode == "probe":
+        # 16 resident build tables (left prefixes of sizes log-uniform in
+        # [1E4, 2E7]); each distinct request probes one of them, its hits
+        # drawn from that table's keys
+        rng = np.random.default_rng(3)
+        sizes = [int(round(np.exp(rng.uniform(np.log(1e4), np.log(2e7))))) for _ in range(16)]
+        tables = []
+        for nt in sizes:
+            tk, tv, to = mdx.mdx_hash_partition(lk[:nt], pay[:nt], 8)
+            tables.append(mdx.mdx_join_build(tk, tv, to, 8))
+        g = torch.Generator(device=dev)
+        g.manual_seed(29)
+        for r in uniq:
+            t = int(rng.integers(0, len(tables)))
+            nt, nr, m = sizes[t], r["nr"], r["m"]
+            hit = lk[torch.randint(0, nt, (m,), generator=g, device=dev)]
+            miss = torch.randint(SERVE_MAX_ROWS, 2 * SERVE_MAX_ROWS, (nr - m,), generator=g, device=dev)
+            r["rk"] = torch.cat([hit, miss])[torch.randperm(nr, generator=g, device=dev)].contiguous()
+            r["table"], r["nl"] = t, nt
+        torch.cuda.synchronize()
+    bad = serving_check_rows(torch, mdx, pool, tables, dev)
+    if bad:
+        raise SystemExit(f"serving: {bad} of {n_unique} distinct requests gave wrong rows")
+    log(f"serving: all {n_unique} distinct requests checked row by row")
     budget = int(args.budget_gb * 1e9)
-    log(f"serving: {n} requests over {args.duration:g} s, offered {rows / args.duration:.4g} rows/s")
+    points = [("rated", args.rate, args.duration), ("overload", args.overload_rate, args.overload_duration)]
     res = {}
-    for label, slots in [("continuous batching", args.slots), ("one merge at a time", 1)]:
-        lat, elapsed = serve_run(torch, mdx, reqs, pool, slots, budget, dev, max_rows)
-        p50, p99 = np.percentile(lat, 50), np.percentile(lat, 99)
-        res[label] = {"slots": slots, "p50_ms": round(float(p50), 3), "p99_ms": round(float(p99), 3),
-                      "max_ms": round(float(max(lat)), 3), "elapsed_s": round(elapsed, 3),
-                      "rows_per_s": round(rows / elapsed, 1)}
-        log(f"  {label} ({slots} slots): p50 {p50:.2f} ms, p99 {p99:.2f} ms, "
-            f"{rows / elapsed:.4g} rows/s over {elapsed:.2f} s")
-    cb = res["continuous batching"]
+    for label, rate, duration in points:
+        rng = np.random.default_rng(1 if label == "rated" else 2)
+        n = int(round(rate * duration))
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, n))
+        picks = rng.integers(0, n_unique, n)
+        stream_reqs = [(float(arrivals[i]), int(picks[i])) for i in range(n)]
+        rows = sum((uniq[u]["nl"] if tables is None else 0) + uniq[u]["nr"] for u in picks)
+        want = torch.tensor([uniq[u]["m"] for u in picks], dtype=torch.int64)
+        log(f"serving {args.serve_mode} at {rate:g}/s for {duration:g} s: {n} requests, "
+            f"offered {rows / duration:.4g} rows/s")
+        res[label] = {"rate_per_s": rate, "duration_s": duration, "requests": n, "input_rows": rows,
+                      "offered_rows_per_s": round(rows / duration, 1)}
+        for policy, slots in [("continuous batching", args.slots), ("FIFO", 1)]:
+            lat, elapsed, totals, st = serve_run(torch, mdx, stream_reqs, pool, slots, budget, dev,
+                                                 args.serve_mode, tables)
+            if int(st.max()) != 0 or not torch.equal(totals, want):
+                raise SystemExit(f"serving: wrong |J| or a device status ({policy}, {label})")
+            p50, p99 = np.percentile(lat, 50), np.percentile(lat, 99)
+            res[label][policy] = {"slots": slots, "p50_ms": round(float(p50), 3),
+                                  "p99_ms": round(float(p99), 3), "max_ms": round(float(max(lat)), 3),
+                                  "elapsed_s": round(elapsed, 3), "rows_per_s": round(rows / elapsed, 1)}
+            log(f"  {policy} ({slots} slots): p50 {p50:.2f} ms, p99 {p99:.2f} ms, "
+                f"{rows / elapsed:.4g} rows/s over {elapsed:.2f} s")
+    cb = res["rated"]["continuous batching"]
+    what = "merge requests (both tables per request)" if tables is None else \
+        "probes of 16 device-resident build tables"
     line = {
-        "metric": "serving p99 latency: Poisson 2000 merge requests/s, 1E4-2E7 rows per side, "
-                  "int64, match fraction U[0.1, 0.9], P=8, 200 GB HBM budget",
+        "metric": f"serving p99 latency: Poisson {args.rate:g} requests/s, 1E4-2E7 rows per side, "
+                  "int64, match fraction U[0.1, 0.9] per request, P=8, "
+                  f"{args.budget_gb:g} GB HBM budget",
         "value": cb["p99_ms"], "unit": "ms",
-        "n_gpus": 1, "steps": n, "warmup": 0, "ms_per_step": round(cb["elapsed_s"] * 1e3 / n, 4),
+        "n_gpus": 1, "steps": res["rated"]["requests"], "warmup": 0,
+        "ms_per_step": round(cb["elapsed_s"] * 1e3 / res["rated"]["requests"], 4),
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "int64", "data": "synthetic",
-        "config": {"workload": f"serving: {n} requests at {args.rate:g}/s over {args.duration:g} s, "
-                               f"{args.slots} slots", "requests": n, "input_rows": rows,
-                   "offered_rows_per_s": round(rows / args.duration, 1)},
-        "modes": res,
+        "config": {"workload": f"serving: {what}, {args.slots} slots, {n_unique} distinct requests "
+                               f"drawn on the device and checked row by row",
+                   "mode": args.serve_mode},
+        "points": res,
     }
     print(json.dumps(line), flush=True)
 

@@ -343,6 +343,34 @@ int32_t mdx_server_create(int32_t slots, int64_t max_left, int64_t max_right, in
 int32_t mdx_server_submit(mdx_server *server, const mdx_merge_desc *h_desc, int64_t tag,
                           hipEvent_t ready, int32_t *h_slot);
 
+/* A probe of a device-resident build table (built once with mdx_join_build),
+ * admitted like a merge: for a service that keeps its build tables on the
+ * device and answers many probe requests against them (each one the join
+ * step of Section V-B's merge, without rebuilding the left table).  The probe
+ * rows (any order) are partitioned by the table's P in the slot's workspace,
+ * then probed with the global-table probe; the outputs are exactly those of
+ * mdx_hash_partition + mdx_join_probe with the same arguments.  The request
+ * holds n (key bytes + 8) + out_capacity (key bytes + 16) + 8 (P + 1) bytes
+ * of the budget.  The caller keeps the table (h_table and its memory) and the
+ * probe's buffers alive and unchanged until the probe is polled.  Errors as
+ * mdx_server_submit, and MDX_ERR_INVALID for a table built by another ABI
+ * version, n > max_right or the table's P > max_P. */
+typedef struct mdx_probe_desc {
+    const void *d_keys;        /* [n] probe keys, the table's key type */
+    const int64_t *d_payload;  /* [n] */
+    int64_t n;
+    void *d_out_key;           /* [out_capacity] output columns, as mdx_join_probe */
+    int64_t *d_out_lpay;
+    int64_t *d_out_rpay;
+    int64_t out_capacity;
+    int64_t *d_out_offsets;    /* [P+1] */
+    int32_t *d_status;         /* may be NULL */
+} mdx_probe_desc;
+
+int32_t mdx_server_submit_probe(mdx_server *server, const mdx_table *h_table,
+                                const mdx_probe_desc *h_desc, int64_t tag, hipEvent_t ready,
+                                int32_t *h_slot);
+
 int32_t mdx_server_poll(mdx_server *server, int64_t *h_tags, int32_t capacity,
                         int32_t *h_count);
 

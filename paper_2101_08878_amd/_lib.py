@@ -64,6 +64,14 @@ class mdx_merge_desc(ctypes.Structure):
     ]
 
 
+class mdx_probe_desc(ctypes.Structure):
+    _fields_ = [
+        ("d_keys", _vp), ("d_payload", _vp), ("n", _i64),
+        ("d_out_key", _vp), ("d_out_lpay", _vp), ("d_out_rpay", _vp), ("out_capacity", _i64),
+        ("d_out_offsets", _vp), ("d_status", _vp),
+    ]
+
+
 def _sig(name, restype, *argtypes):
     f = getattr(_lib, name)
     f.restype = restype
@@ -97,6 +105,8 @@ _srv_create = _sig("mdx_server_create", _i32, _i32, _i64, _i64, _i32, _sz, _vp, 
                    ctypes.POINTER(_vp))
 _srv_submit = _sig("mdx_server_submit", _i32, _vp, ctypes.POINTER(mdx_merge_desc), _i64, _vp,
                    ctypes.POINTER(_i32))
+_srv_submit_probe = _sig("mdx_server_submit_probe", _i32, _vp, ctypes.POINTER(mdx_table),
+                         ctypes.POINTER(mdx_probe_desc), _i64, _vp, ctypes.POINTER(_i32))
 _srv_poll = _sig("mdx_server_poll", _i32, _vp, ctypes.POINTER(_i64), _i32, ctypes.POINTER(_i32))
 _srv_stats = _sig("mdx_server_stats", _i32, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_sz))
 _srv_destroy = _sig("mdx_server_destroy", _i32, _vp)
@@ -112,7 +122,8 @@ ABI_FUNCTIONS = [
     "mdx_join_probe_workspace_bytes", "mdx_join_probe",
     "mdx_merge_workspace_bytes", "mdx_merge",
     "mdx_merge_batch_workspace_bytes", "mdx_merge_batch",
-    "mdx_server_workspace_bytes", "mdx_server_create", "mdx_server_submit", "mdx_server_poll",
+    "mdx_server_workspace_bytes", "mdx_server_create", "mdx_server_submit",
+    "mdx_server_submit_probe", "mdx_server_poll",
     "mdx_server_stats", "mdx_server_destroy",
     "mdx_transpose_sum",
     "mdx_trace_kernel",
@@ -184,6 +195,23 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
     return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
 
 
+def _handoff(stream, made):
+    """Tensors allocated here (`made`: workspaces, missing outputs) come from
+    the current stream's pool; when the work goes to another stream, that
+    stream first waits for the current one (so it never touches memory the
+    current stream's earlier work still uses) and the tensors are marked as
+    used on it (so the allocator hands them out again only after that work)."""
+    made = [t for t in made if t is not None]
+    if stream is None or not made:
+        return
+    cur = torch.cuda.current_stream(made[0].device)
+    if stream == cur:
+        return
+    stream.wait_stream(cur)
+    for t in made:
+        t.record_stream(stream)
+
+
 # ---- hash partition ------------------------------------------------------------
 
 def mdx_hash_partition_workspace_bytes(n: int, P: int, key_type: int = MDX_KEY_I64) -> int:
@@ -197,11 +225,20 @@ def mdx_hash_partition(keys: torch.Tensor, payload: torch.Tensor, P: int, *, key
     n = keys.numel()
     kt = _key_type(keys)
     dev = keys.device
-    keys_out = torch.empty_like(keys) if keys_out is None else keys_out
-    payload_out = torch.empty(n, dtype=torch.int64, device=dev) if payload_out is None else payload_out
-    offsets = torch.empty(P + 1, dtype=torch.int64, device=dev) if offsets is None else offsets
-    need = mdx_hash_partition_workspace_bytes(n, P, kt)
-    workspace = _workspace(need, dev) if workspace is None else workspace
+    made = []
+    if keys_out is None:
+        keys_out = torch.empty_like(keys)
+        made.append(keys_out)
+    if payload_out is None:
+        payload_out = torch.empty(n, dtype=torch.int64, device=dev)
+        made.append(payload_out)
+    if offsets is None:
+        offsets = torch.empty(P + 1, dtype=torch.int64, device=dev)
+        made.append(offsets)
+    if workspace is None:
+        workspace = _workspace(mdx_hash_partition_workspace_bytes(n, P, kt), dev)
+        made.append(workspace)
+    _handoff(stream, made)
     _check(_part(_dev(keys, "keys"), _dev(payload, "payload", torch.int64, n), n, kt, int(P),
                  _dev(keys_out, "keys_out", keys.dtype, n), _dev(payload_out, "payload_out", torch.int64, n),
                  _dev(offsets, "offsets", torch.int64, P + 1), _dev(workspace, "workspace"),
@@ -246,6 +283,7 @@ def mdx_join_build(keys: torch.Tensor, payload: torch.Tensor, offsets: torch.Ten
     kt = _key_type(keys)
     need = mdx_join_table_bytes(n, P, kt)
     mem = _workspace(need, keys.device) if table_memory is None else table_memory
+    _handoff(stream, [mem] if table_memory is None else [])
     t = mdx_table()
     _check(_build(_dev(keys, "keys"), _dev(payload, "payload", torch.int64, n),
                   _dev(offsets, "offsets", torch.int64, P + 1), n, int(P), kt, _dev(mem, "table_memory"),
@@ -278,10 +316,17 @@ def mdx_join_probe(table: Table, keys: torch.Tensor, payload: torch.Tensor, offs
     P = table.P
     kt = _key_type(keys)
     dev = keys.device
+    made = []
     ok, ol, orr = _outputs(out_capacity, keys.dtype, dev, out)
-    out_offsets = torch.empty(P + 1, dtype=torch.int64, device=dev) if out_offsets is None else out_offsets
-    need = mdx_join_probe_workspace_bytes(n, P, kt)
-    workspace = _workspace(need, dev) if workspace is None else workspace
+    if out is None:
+        made += [ok, ol, orr]
+    if out_offsets is None:
+        out_offsets = torch.empty(P + 1, dtype=torch.int64, device=dev)
+        made.append(out_offsets)
+    if workspace is None:
+        workspace = _workspace(mdx_join_probe_workspace_bytes(n, P, kt), dev)
+        made.append(workspace)
+    _handoff(stream, made)
     _check(_probe(ctypes.byref(table.struct), _dev(keys, "keys"), _dev(payload, "payload", torch.int64, n),
                   _dev(offsets, "offsets", torch.int64, P + 1), n, _dev(workspace, "workspace"),
                   workspace.numel() * workspace.element_size(),
@@ -309,10 +354,17 @@ def mdx_merge(left_keys: torch.Tensor, left_payload: torch.Tensor, right_keys: t
     if right_keys.dtype != left_keys.dtype:
         raise TypeError("left and right keys must have the same dtype")
     dev = left_keys.device
+    made = []
     ok, ol, orr = _outputs(out_capacity, left_keys.dtype, dev, out)
-    out_offsets = torch.empty(P + 1, dtype=torch.int64, device=dev) if out_offsets is None else out_offsets
-    need = mdx_merge_workspace_bytes(nl, nr, P, kt)
-    workspace = _workspace(need, dev) if workspace is None else workspace
+    if out is None:
+        made += [ok, ol, orr]
+    if out_offsets is None:
+        out_offsets = torch.empty(P + 1, dtype=torch.int64, device=dev)
+        made.append(out_offsets)
+    if workspace is None:
+        workspace = _workspace(mdx_merge_workspace_bytes(nl, nr, P, kt), dev)
+        made.append(workspace)
+    _handoff(stream, made)
     _check(_merge(_dev(left_keys, "left_keys"), _dev(left_payload, "left_payload", torch.int64, nl), nl,
                   _dev(right_keys, "right_keys"), _dev(right_payload, "right_payload", torch.int64, nr), nr,
                   kt, int(P), _dev(workspace, "workspace"), workspace.numel() * workspace.element_size(),
@@ -362,6 +414,18 @@ class MergeJob:
     status: torch.Tensor | None = None
 
 
+@dataclass
+class ProbeJob:
+    """One probe of a device-resident table (Server.submit_probe)."""
+    table: "Table"
+    keys: torch.Tensor
+    payload: torch.Tensor
+    out_capacity: int
+    out: tuple | None = None
+    out_offsets: torch.Tensor | None = None
+    status: torch.Tensor | None = None
+
+
 def _batch_descs(jobs, with_pointers: bool):
     descs = (mdx_merge_desc * max(len(jobs), 1))()
     for i, j in enumerate(jobs):
@@ -393,16 +457,21 @@ def mdx_merge_batch(jobs, *, lanes: int = 4, workspace=None, stream=None):
     """Run every MergeJob as mdx_merge would, on up to `lanes` concurrent
     lanes.  Missing outputs are allocated here.  Asynchronous; returns the
     jobs with their outputs filled in."""
+    made = []
     for j in jobs:
         dev = j.left_keys.device
         if j.out is None:
             j.out = _outputs(j.out_capacity, j.left_keys.dtype, dev, None)
+            made += list(j.out)
         if j.out_offsets is None:
             j.out_offsets = torch.empty(j.P + 1, dtype=torch.int64, device=dev)
+            made.append(j.out_offsets)
     if workspace is None:
         need = mdx_merge_batch_workspace_bytes(jobs, lanes)
         dev = jobs[0].left_keys.device if jobs else torch.device("cuda")
         workspace = _workspace(need, dev)
+        made.append(workspace)
+    _handoff(stream, made)
     descs = _batch_descs(jobs, True)
     _check(_batch(len(jobs), descs, int(lanes), _dev(workspace, "workspace"),
                   workspace.numel() * workspace.element_size(), _stream(stream)))
@@ -435,6 +504,19 @@ class Server:
         self._tags = (_i64 * int(slots))()
         self._jobs = {}
 
+    @staticmethod
+    def _ready(ready):
+        """The event a request waits for before reading its inputs: by
+        default one recorded now on the current stream, which orders the
+        inputs written there and the outputs allocated there before the
+        slot's stream; 0 waits for nothing (inputs and outputs already
+        complete).  Returns (handle, event kept alive until submitted)."""
+        if ready is not None:
+            return ready, None
+        ev = torch.cuda.Event()
+        ev.record(torch.cuda.current_stream())
+        return ev.cuda_event, ev
+
     def submit(self, job: MergeJob, tag: int, ready=None):
         if self._h is None:
             raise MdxError(MDX_ERR_INVALID, "server is closed")
@@ -445,7 +527,41 @@ class Server:
             job.out_offsets = torch.empty(job.P + 1, dtype=torch.int64, device=dev)
         desc = _batch_descs([job], True)
         slot = _i32(-1)
-        st = _srv_submit(self._h, desc, int(tag), ready, ctypes.byref(slot))
+        handle, _keep = self._ready(ready)
+        st = _srv_submit(self._h, desc, int(tag), handle, ctypes.byref(slot))
+        if st == MDX_BUSY:
+            return None
+        _check(st)
+        self._jobs[int(tag)] = job
+        return slot.value
+
+    def submit_probe(self, job: "ProbeJob", tag: int, ready=None):
+        """Probe job.table (built once with mdx_join_build, kept on the
+        device) with job's rows in a free slot; None when no slot or budget
+        is free (nothing enqueued)."""
+        if self._h is None:
+            raise MdxError(MDX_ERR_INVALID, "server is closed")
+        t = job.table
+        dev = job.keys.device
+        if job.out is None:
+            job.out = _outputs(job.out_capacity, job.keys.dtype, dev, None)
+        if job.out_offsets is None:
+            job.out_offsets = torch.empty(t.P + 1, dtype=torch.int64, device=dev)
+        n, cap = job.keys.numel(), int(job.out_capacity)
+        d = mdx_probe_desc()
+        d.d_keys = _dev(job.keys, "keys")
+        d.d_payload = _dev(job.payload, "payload", torch.int64, n)
+        d.n = n
+        d.d_out_key = _dev(job.out[0], "out_key", job.keys.dtype, cap)
+        d.d_out_lpay = _dev(job.out[1], "out_lpay", torch.int64, cap)
+        d.d_out_rpay = _dev(job.out[2], "out_rpay", torch.int64, cap)
+        d.out_capacity = cap
+        d.d_out_offsets = _dev(job.out_offsets, "out_offsets", torch.int64, t.P + 1)
+        d.d_status = _dev(job.status, "status", torch.int32, 1) if job.status is not None else None
+        slot = _i32(-1)
+        handle, _keep = self._ready(ready)
+        st = _srv_submit_probe(self._h, ctypes.byref(t.struct), ctypes.byref(d), int(tag), handle,
+                               ctypes.byref(slot))
         if st == MDX_BUSY:
             return None
         _check(st)

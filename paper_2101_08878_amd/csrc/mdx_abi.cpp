@@ -971,6 +971,42 @@ size_t request_bytes(const mdx_merge_desc &d)
            (size_t)d.out_capacity * ((size_t)d.key_type + 16) + (size_t)(d.P + 1) * 8;
 }
 
+// Bytes a probe against a resident table holds while it runs.
+size_t probe_request_bytes(const mdx_probe_desc &d, int32_t P, int32_t key_type)
+{
+    return (size_t)d.n * ((size_t)key_type + 8) +
+           (size_t)d.out_capacity * ((size_t)key_type + 16) + (size_t)(P + 1) * 8;
+}
+
+// A probe job's slot workspace: the probe rows partitioned by the table's P
+// (partition workspace, keys, payloads, offsets), then the probe workspace.
+struct ProbeJobLayout {
+    PartLayout pl;
+    ProbeLayout ql;
+    size_t part_off, keys_off, pay_off, off_off, probe_off, bytes;
+};
+
+ProbeJobLayout probe_job_layout(int64_t n, int32_t P, int32_t kt)
+{
+    ProbeJobLayout L;
+    L.pl = part_layout(n, P);
+    L.ql = probe_layout(n, P);
+    const size_t k = (size_t)(n > 0 ? n : 1);
+    size_t o = 0;
+    L.part_off = o;
+    o += align_up(L.pl.bytes);
+    L.keys_off = o;
+    o += align_up(k * (size_t)kt);
+    L.pay_off = o;
+    o += align_up(k * 8);
+    L.off_off = o;
+    o += align_up((size_t)(P + 1) * 8);
+    L.probe_off = o;
+    o += align_up(L.ql.bytes);
+    L.bytes = o;
+    return L;
+}
+
 int32_t check_server_limits(int32_t slots, int64_t max_left, int64_t max_right, int32_t max_P,
                             const char *W)
 {
@@ -1090,6 +1126,83 @@ int32_t mdx_server_submit(mdx_server *srv, const mdx_merge_desc *h_desc, int64_t
     srv->held[(size_t)s] = need;
     srv->in_flight += need;
     *h_slot = s;
+    return MDX_OK;
+}
+
+int32_t mdx_server_submit_probe(mdx_server *srv, const mdx_table *h_table,
+                                const mdx_probe_desc *h_desc, int64_t tag, hipEvent_t ready,
+                                int32_t *h_slot)
+{
+    g_err.clear();
+    const char *W = "mdx_server_submit_probe";
+    if (!srv || !h_table || !h_desc || !h_slot)
+        return fail(MDX_ERR_INVALID, std::string(W) + ": null server, table, descriptor or h_slot");
+    const mdx_table &t = *h_table;
+    if (t.abi_version != MDX_ABI_VERSION || !t.d_slots)
+        return fail(MDX_ERR_INVALID, std::string(W) + ": table missing or built by another ABI version");
+    const mdx_probe_desc &d = *h_desc;
+    const int32_t P = t.P, kt = t.key_type;
+    if (int32_t e = check_sizes(d.n, P, kt, W))
+        return e;
+    if (int32_t e = check_columns(d.d_keys, d.d_payload, d.n, kt, W))
+        return e;
+    if (int32_t e = check_outputs(d.d_out_key, d.d_out_lpay, d.d_out_rpay, d.out_capacity, kt,
+                                  d.d_out_offsets, d.d_status, W))
+        return e;
+    if (d.n > srv->max_right || P > srv->max_P)
+        return fail(MDX_ERR_INVALID, std::string(W) + ": probe larger than the server's limits");
+    const size_t need = probe_request_bytes(d, P, kt);
+    if (need > srv->budget)
+        return fail(MDX_ERR_INVALID, std::string(W) + ": probe alone exceeds the memory budget");
+    const ProbeJobLayout L = probe_job_layout(d.n, P, kt);
+    if (L.bytes > srv->slot_bytes)  // a merge slot always holds a probe job of its limits
+        return fail(MDX_ERR_WORKSPACE, std::string(W) + ": slot workspace too small for the probe");
+    const size_t kb = (size_t)d.out_capacity * (size_t)kt, vb = (size_t)d.out_capacity * 8;
+    const size_t ws_all = (size_t)srv->slots * srv->slot_bytes;
+    if (overlap(srv->d_ws, ws_all, d.d_out_key, kb) || overlap(srv->d_ws, ws_all, d.d_out_lpay, vb) ||
+        overlap(srv->d_ws, ws_all, d.d_out_rpay, vb) || overlap(t.d_mem, t.bytes, d.d_out_key, kb) ||
+        overlap(t.d_mem, t.bytes, d.d_out_lpay, vb) || overlap(t.d_mem, t.bytes, d.d_out_rpay, vb))
+        return fail(MDX_ERR_INVALID, std::string(W) + ": output overlaps the workspace or the table");
+    *h_slot = -1;
+    int32_t sl = -1;
+    for (int32_t i = 0; i < srv->slots; ++i)
+        if (!srv->busy[(size_t)i]) {
+            sl = i;
+            break;
+        }
+    if (sl < 0 || srv->in_flight + need > srv->budget)
+        return MDX_BUSY;
+    char *b = srv->d_ws + (size_t)sl * srv->slot_bytes;
+    void *pk = b + L.keys_off;
+    int64_t *pv = (int64_t *)(b + L.pay_off), *poff = (int64_t *)(b + L.off_off);
+    const ProbeWs w = probe_ws(b + L.probe_off, L.ql);
+    ProbeOut o;
+    o.key = d.d_out_key;
+    o.lpay = d.d_out_lpay;
+    o.rpay = d.d_out_rpay;
+    o.cap = d.out_capacity;
+    o.offsets = d.d_out_offsets;
+    hipStream_t st = srv->streams[(size_t)sl];
+    hipError_t e = ready ? hipStreamWaitEvent(st, ready, 0) : hipSuccess;
+    const PartArgs pa = {d.d_keys, d.d_payload, d.n, pk, pv, poff, nullptr, b + L.part_off};
+    if (e == hipSuccess)
+        e = launch_partition(&pa, 1, kt, P, 0, 0, 0, st);
+    if (e == hipSuccess)
+        e = launch_probe_plan(poff, d.n, P, w, nullptr, st);
+    if (e == hipSuccess)
+        e = launch_probe_group(pk, pv, kt, P, make_view(t, t.d_offsets, 0, P), 0, w, o, d.d_status,
+                               0, st);
+    if (e == hipSuccess)
+        e = launch_probe_finalize(P, w, o, nullptr, st);
+    if (e == hipSuccess)
+        e = hipEventRecord(srv->done[(size_t)sl], st);
+    if (e != hipSuccess)
+        return hip_fail(e, W);
+    srv->busy[(size_t)sl] = 1;
+    srv->tag[(size_t)sl] = tag;
+    srv->held[(size_t)sl] = need;
+    srv->in_flight += need;
+    *h_slot = sl;
     return MDX_OK;
 }
 

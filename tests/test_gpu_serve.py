@@ -101,3 +101,92 @@ def test_server_budget_admission():
         got = dict(key=host(j.out[0]), lpay=host(j.out[1]), rpay=host(j.out[2]),
                    off=host(j.out_offsets), status=int(j.status.item()), cap=j.out_capacity)
         assert_join_equals_oracle(kl, vl, kr, vr, P, got)
+
+
+def _tables_and_probes(seed):
+    """Three build tables to keep on the device (in one every key appears 4
+    times) and 30 probe requests against them, each with its own match
+    fraction drawn from U[0.1, 0.9]."""
+    rng = np.random.default_rng(seed)
+    tables = []
+    for n, P in [(250_000, 8), (40_000, 8), (120_000, 5)]:
+        kl = rng.permutation(n).astype(np.int64)
+        if n == 120_000:
+            kl = (kl % 30_000).astype(np.int64)  # every key 4 times
+        tables.append((kl, np.arange(n, dtype=np.int64) * 3 + 1, P))
+    probes = []
+    for i in range(30):
+        t = int(rng.integers(0, len(tables)))
+        kl = tables[t][0]
+        nr = int(round(np.exp(rng.uniform(np.log(1e3), np.log(2e5)))))
+        f = float(rng.uniform(0.1, 0.9))
+        m = int(round(f * nr))
+        hit = kl[rng.integers(0, kl.size, m)]
+        miss = rng.integers(1 << 40, 1 << 41, nr - m)
+        kr = np.concatenate([hit, miss])[rng.permutation(nr)].astype(np.int64)
+        probes.append((t, kr, np.arange(nr, dtype=np.int64) * 7 - 2))
+    return tables, probes
+
+
+def test_server_probes_of_resident_tables_equal_alone():
+    """Build tables once (mdx_join_build), then admit probe requests against
+    them into 4 slots: each result equals the same probe run alone
+    (mdx_hash_partition + mdx_join_probe) and the oracle."""
+    import paper_2101_08878_amd as mdx
+    announce("server: 30 probes of 3 resident tables, 4 slots")
+    tables, probes = _tables_and_probes(11)
+    built = []
+    for kl, vl, P in tables:
+        lk, lv, lo = mdx.mdx_hash_partition(dev(kl), dev(vl), P)
+        st = torch.zeros(1, dtype=torch.int32, device="cuda")
+        built.append(mdx.mdx_join_build(lk, lv, lo, P, status=st))
+        torch.cuda.synchronize()
+        assert int(st.item()) == 0
+    jobs = []
+    for t, kr, vr in probes:
+        cap = int(kr.size) * (4 if t == 2 else 1)
+        jobs.append(mdx.ProbeJob(built[t], dev(kr), dev(vr), cap,
+                                 status=torch.zeros(1, dtype=torch.int32, device="cuda")))
+    pending, done = list(range(len(jobs))), []
+    with mdx.Server(4, 300_000, 300_000, 8, 1 << 34) as srv:
+        while pending or len(done) < len(jobs):
+            while pending and srv.submit_probe(jobs[pending[0]], pending[0]) is not None:
+                pending.pop(0)
+            done += srv.poll()
+        assert sorted(done) == list(range(len(jobs)))
+        assert srv.stats() == (0, 0)
+    torch.cuda.synchronize()
+    for i, ((t, kr, vr), j) in enumerate(zip(probes, jobs)):
+        kl, vl, P = tables[t]
+        total = int(j.out_offsets[-1].item())
+        assert int(j.status.item()) == 0, i
+        mix = dict(key=host(j.out[0]), lpay=host(j.out[1]), rpay=host(j.out[2]),
+                   off=host(j.out_offsets), status=0, cap=j.out_capacity)
+        rk, rv, ro = mdx.mdx_hash_partition(dev(kr), dev(vr), P)
+        ok, ol, orr, off = mdx.mdx_join_probe(built[t], rk, rv, ro, out_capacity=j.out_capacity)
+        torch.cuda.synchronize()
+        assert np.array_equal(mix["off"], host(off)), i
+        for a, b in zip(canonical(mix["key"][:total], mix["lpay"][:total], mix["rpay"][:total]),
+                        canonical(host(ok)[:total], host(ol)[:total], host(orr)[:total])):
+            assert np.array_equal(a, b), i
+        assert_join_equals_oracle(kl, vl, kr, vr, P, mix)
+
+
+def test_server_probe_rejects_what_it_cannot_admit():
+    """Host checks of a probe request: a probe beyond the server's limits and
+    a table of a larger P are refused with MDX_ERR_INVALID, nothing runs."""
+    import paper_2101_08878_amd as mdx
+    announce("server: probe limits")
+    kl = np.arange(1000, dtype=np.int64)
+    lk, lv, lo = mdx.mdx_hash_partition(dev(kl), dev(kl), 16)
+    t16 = mdx.mdx_join_build(lk, lv, lo, 16)
+    kr = dev(np.arange(5000, dtype=np.int64))
+    with mdx.Server(2, 2000, 2000, 8, 1 << 30) as srv:
+        with pytest.raises(mdx.MdxError):
+            srv.submit_probe(mdx.ProbeJob(t16, kr[:100], kr[:100], 100), 0)  # P = 16 > max_P
+        lk8, lv8, lo8 = mdx.mdx_hash_partition(dev(kl), dev(kl), 8)
+        t8 = mdx.mdx_join_build(lk8, lv8, lo8, 8)
+        with pytest.raises(mdx.MdxError):
+            srv.submit_probe(mdx.ProbeJob(t8, kr, kr, 5000), 1)  # n > max_right
+        assert srv.stats() == (0, 0)
+    torch.cuda.synchronize()
