@@ -408,7 +408,8 @@ int32_t mdx_transpose_sum(const double *d_x, double *d_y, int64_t n, hipStream_t
  * alive while tracing.  Up to 16 kernels can be traced at once; kernel ==
  * NULL stops all tracing on the thread.  Names: "part_hist", "part_scatter",
  * "seg_hist", "seg_scatter", "rj_join", "tbl_init", "tbl_insert",
- * "probe_chain", "probe_expand", "transpose_sum".
+ * "grp_count", "grp_alloc", "grp_scatter", "probe_chain", "probe_expand",
+ * "transpose_sum".
  * ------------------------------------------------------------------------- */
 int32_t mdx_trace_kernel(const char *kernel, hipEvent_t *h_starts, hipEvent_t *h_stops,
                          int32_t capacity, int32_t *h_count);

@@ -128,7 +128,8 @@ ABI_FUNCTIONS = [
     "mdx_transpose_sum",
     "mdx_trace_kernel",
 ]
-TRACEABLE_KERNELS = ["part_hist", "part_scatter", "seg_hist", "seg_scatter", "rj_join",
+TRACEABLE_KERNELS = ["part_hist", "part_scatter", "seg_hist", "seg_scatter", "rj_join", "grp_count",
+                     "grp_alloc", "grp_scatter",
                      "tbl_init", "tbl_insert", "probe_chain", "probe_expand", "transpose_sum"]
 
 

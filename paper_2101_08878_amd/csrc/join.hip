@@ -14,7 +14,11 @@
 // a repeated key.  Only such partitions then run the grouped build
 // (grp_reset, grp_count, grp_alloc, grp_scatter), which turns the value into
 // a cursor and lays the partition's payloads out grouped by key
-// ("grouped", with [gstart[s], value[s]) the group of slot s).
+// ("grouped", with [gstart[s], value[s]) the group of slot s).  A key can
+// hold millions of rows (a Zipf distribution's first key), so rows are
+// counted and placed per workgroup first: a workgroup's rows of one slot
+// meet in an LDS map and reach the slot with one global atomic, and group
+// starts are allocated per chunk of slots, not per wave.
 //
 // Probe (probe_chain): tiles of 2048 probe rows, each inside one partition,
 // are taken in order from a ticket counter.  A tile looks up its rows,
@@ -25,6 +29,8 @@
 // directly; tiles of repeated-key partitions record per-row prefixes and are
 // expanded by probe_expand, which spreads a tile's output over the whole
 // device in chunks (one right row can match millions of left rows).
+#include <algorithm>
+
 #include "mdx.h"
 #include "mdx_internal.hpp"
 
@@ -174,7 +180,10 @@ __global__ __launch_bounds__(kBlock) void tbl_insert(const K *__restrict__ keys,
                 w = expect;
             }
             if (w == h) {
-                v.flags[p] = 1;  // repeated key
+                // repeated key: one store per partition suffices (a key can
+                // repeat millions of times, each a store to one address)
+                if (!v.flags[p])
+                    v.flags[p] = 1;
                 break;
             }
             if (++i == (uint64_t)H)
@@ -215,7 +224,64 @@ __device__ __forceinline__ int64_t dup_row_slot(const K *keys, const TView &v, i
     return find_slot(v.slots, sb, H, h);
 }
 
-// value[s] += rows of the slot's key (wave-aggregated per slot).
+// ---- per-workgroup aggregation of rows by slot ------------------------------------
+constexpr int kAggRows = 16384;  // rows per workgroup of grp_count / grp_scatter
+constexpr int kAggMap = 2048;    // LDS map entries: slot -> rows of this workgroup
+constexpr int kAggProbe = 8;     // map probes before a row goes to the slot directly
+constexpr int64_t kAggNone = -1;
+
+__device__ __forceinline__ uint32_t agg_home(int64_t s)
+{
+    return ((uint32_t)s * 0x9E3779B1u) >> (32 - 11);
+}
+static_assert(kAggMap == 1 << 11, "agg_home takes 11 bits");
+
+// Entry of slot s in the map, inserting it if there is room within
+// kAggProbe probes; -1 otherwise.  Entries are never removed, so every row of
+// one slot gets the same answer.
+__device__ __forceinline__ int agg_insert(int64_t *mkey, int64_t s)
+{
+    uint32_t h = agg_home(s);
+    for (int k = 0; k < kAggProbe; ++k) {
+        int64_t cur = mkey[h];
+        if (cur == kAggNone) {
+            cur = (int64_t)atomicCAS((unsigned long long *)&mkey[h], (unsigned long long)kAggNone,
+                                     (unsigned long long)s);
+            if (cur == kAggNone)
+                return (int)h;
+        }
+        if (cur == s)
+            return (int)h;
+        h = (h + 1) & (kAggMap - 1);
+    }
+    return -1;
+}
+
+// Entry of slot s if the map holds it, else -1 (the map is complete).
+__device__ __forceinline__ int agg_find(const int64_t *mkey, int64_t s)
+{
+    uint32_t h = agg_home(s);
+    for (int k = 0; k < kAggProbe; ++k) {
+        const int64_t cur = mkey[h];
+        if (cur == s)
+            return (int)h;
+        if (cur == kAggNone)
+            return -1;
+        h = (h + 1) & (kAggMap - 1);
+    }
+    return -1;
+}
+
+// Rows of workgroup b: [o0 + b kAggRows, ...) of the view's rows.
+__device__ __forceinline__ void agg_rows(const TView &v, int64_t &o0, int64_t &r0, int64_t &r1)
+{
+    o0 = v.off[v.pb];
+    const int64_t o1 = v.off[v.pe];
+    r0 = o0 + (int64_t)blockIdx.x * kAggRows;
+    r1 = r0 + kAggRows < o1 ? r0 + kAggRows : o1;
+}
+
+// value[s] += rows of the slot's key.
 template <typename K>
 __global__ __launch_bounds__(kBlock) void grp_count(const K *__restrict__ keys, TView v)
 {
@@ -223,75 +289,98 @@ __global__ __launch_bounds__(kBlock) void grp_count(const K *__restrict__ keys, 
         return;
     if (!block_any_dup(v))
         return;
-    const int64_t o0 = v.off[v.pb], o1 = v.off[v.pe];
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    const int lane = lane_id();
-    for (int64_t b = o0 + (int64_t)blockIdx.x * kBlock; b < o1; b += stride) {
-        const int64_t s = dup_row_slot(keys, v, o0, b + threadIdx.x, o1);
-        uint64_t active = ballot(s >= 0);
-        while (active) {
-            const int leader = __ffsll((unsigned long long)active) - 1;
-            const int64_t ls = __shfl(s, leader, kWave);
-            const uint64_t mask = ballot(s == ls) & active;
-            if (lane == leader)
-                atomicAdd((unsigned long long *)&v.slots[2 * ls + 1],
-                          (unsigned long long)__popcll(mask));
-            active &= ~mask;
-        }
+    __shared__ int64_t mkey[kAggMap];
+    __shared__ uint32_t mcnt[kAggMap];
+    for (int i = threadIdx.x; i < kAggMap; i += kBlock) {
+        mkey[i] = kAggNone;
+        mcnt[i] = 0;
     }
+    __syncthreads();
+    int64_t o0, r0, r1;
+    agg_rows(v, o0, r0, r1);
+    const int64_t o1 = v.off[v.pe];
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += kBlock) {
+        const int64_t s = dup_row_slot(keys, v, o0, r, o1);
+        if (s < 0)
+            continue;
+        const int e = agg_insert(mkey, s);
+        if (e >= 0)
+            atomicAdd(&mcnt[e], 1u);
+        else
+            atomicAdd((unsigned long long *)&v.slots[2 * s + 1], 1ull);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kAggMap; i += kBlock)
+        if (mkey[i] != kAggNone)
+            atomicAdd((unsigned long long *)&v.slots[2 * mkey[i] + 1], (unsigned long long)mcnt[i]);
 }
 
 // Give every key of a repeated-key partition its range of the grouped array:
-// gstart[s] = value[s] = (partition's first row) + running total.
+// gstart[s] = value[s] = (partition's first row) + running total.  Workgroup b
+// takes the slots [b kAllocSlots, (b+1) kAllocSlots): per partition in it, a
+// sum over its slots, one atomic on the partition's allocator, then the
+// exclusive scan of its slots' counts from there.
+constexpr int64_t kAllocSlots = 65536;
+
+__device__ __forceinline__ int64_t slot_rows(const TView &v, const int64_t *slots2, int64_t s,
+                                             int64_t sb, int64_t H)
+{
+    const uint64_t w = v.slots[2 * s];
+    const uint64_t empty = empty_of_half((s - sb) >= H ? 1 : 0);
+    return w == empty ? 0 : (int64_t)slots2[2 * s + 1];
+}
+
 __global__ __launch_bounds__(kBlock) void grp_alloc(TView v)
 {
     if (skipped(v.skip))
         return;
     if (!block_any_dup(v))
         return;
+    __shared__ int64_t scratch[kWavesPerBlock];
+    __shared__ int64_t s_base;
     const int64_t o0 = v.off[v.pb];
     const int64_t total = 2 * (v.off[v.pe] - o0) + 16 * (int64_t)(v.pe - v.pb);
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    const int lane = lane_id();
-    for (int64_t b = (int64_t)blockIdx.x * kBlock; b < total; b += stride) {
-        const int64_t s = b + threadIdx.x;
-        int p = -1;
-        int64_t c = 0;
-        if (s < total) {
-            p = slot_part(v, o0, s);
-            int64_t sb, H;
-            part_slots(v, o0, p, sb, H);
-            const uint64_t w = v.slots[2 * s];
-            const uint64_t empty = empty_of_half((s - sb) >= H ? 1 : 0);
-            if (!v.flags[p] || w == empty)
-                p = -1;
-            else
-                c = (int64_t)v.slots[2 * s + 1];
-        }
-        uint64_t active = ballot(p >= 0);
-        while (active) {
-            const int leader = __ffsll((unsigned long long)active) - 1;
-            const int lp = __shfl(p, leader, kWave);
-            const uint64_t mask = ballot(p == lp) & active;
-            const bool mine = (mask >> lane) & 1ull;
-            const int64_t incl = wave_incl_scan(mine ? c : 0, lane);
-            const int64_t sum = __shfl(incl, kWave - 1, kWave);
-            int64_t base = 0;
-            if (lane == leader)
-                base = (int64_t)atomicAdd((unsigned long long *)&v.bump[lp],
-                                          (unsigned long long)sum);
-            base = __shfl(base, leader, kWave);
-            if (mine) {
-                const int64_t start = (v.off[lp] - o0) + base + incl - c;
-                v.gstart[s] = start;
-                v.slots[2 * s + 1] = (uint64_t)start;
+    const int64_t c0 = (int64_t)blockIdx.x * kAllocSlots;
+    const int64_t c1 = c0 + kAllocSlots < total ? c0 + kAllocSlots : total;
+    if (c0 >= c1)
+        return;
+    const int64_t *sv = (const int64_t *)v.slots;
+    for (int p = slot_part(v, o0, c0); p < v.pe; ++p) {
+        int64_t sb, H;
+        part_slots(v, o0, p, sb, H);
+        if (sb >= c1)
+            break;
+        if (!v.flags[p])
+            continue;
+        const int64_t a = sb > c0 ? sb : c0, e = sb + 2 * H < c1 ? sb + 2 * H : c1;
+        int64_t sum = 0;
+        for (int64_t x = a + threadIdx.x; x < e; x += kBlock)
+            sum += slot_rows(v, sv, x, sb, H);
+        int64_t all;
+        (void)block_excl_scan(sum, scratch, &all);
+        if (threadIdx.x == 0)
+            s_base = (int64_t)atomicAdd((unsigned long long *)&v.bump[p], (unsigned long long)all);
+        __syncthreads();
+        int64_t carry = (v.off[p] - o0) + s_base;
+        for (int64_t x0 = a; x0 < e; x0 += kBlock) {
+            const int64_t x = x0 + threadIdx.x;
+            const int64_t c = x < e ? slot_rows(v, sv, x, sb, H) : 0;
+            int64_t tot;
+            const int64_t ex = block_excl_scan(c, scratch, &tot);
+            if (x < e && c > 0) {
+                v.gstart[x] = carry + ex;
+                v.slots[2 * x + 1] = (uint64_t)(carry + ex);
             }
-            active &= ~mask;
+            carry += tot;
         }
+        __syncthreads();  // s_base is reused by the next partition
     }
 }
 
 // grouped[value[s]++] = payload, for every row of a repeated-key partition.
+// First the workgroup counts its rows per slot in the map and reserves one
+// range per slot; then every row takes the next place of its slot's range
+// (rows the map could not hold take a place from the slot directly).
 template <typename K>
 __global__ __launch_bounds__(kBlock) void grp_scatter(const K *__restrict__ keys,
                                                       const int64_t *__restrict__ pay, TView v)
@@ -300,26 +389,56 @@ __global__ __launch_bounds__(kBlock) void grp_scatter(const K *__restrict__ keys
         return;
     if (!block_any_dup(v))
         return;
-    const int64_t o0 = v.off[v.pb], o1 = v.off[v.pe];
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    const int lane = lane_id();
-    for (int64_t b = o0 + (int64_t)blockIdx.x * kBlock; b < o1; b += stride) {
-        const int64_t r = b + threadIdx.x;
+    __shared__ int64_t mkey[kAggMap];
+    __shared__ int64_t mbase[kAggMap];
+    __shared__ uint32_t mcnt[kAggMap];
+    // every row's map entry from the first pass: kRowSkip (no repeated-key
+    // row), kRowDirect (not in the map: takes its place from the slot), or
+    // the entry
+    constexpr int16_t kRowSkip = -2, kRowDirect = -1;
+    __shared__ int16_t rent[kAggRows];
+    for (int i = threadIdx.x; i < kAggMap; i += kBlock) {
+        mkey[i] = kAggNone;
+        mcnt[i] = 0;
+    }
+    __syncthreads();
+    int64_t o0, r0, r1;
+    agg_rows(v, o0, r0, r1);
+    const int64_t o1 = v.off[v.pe];
+    for (int i = threadIdx.x; i < kAggRows; i += kBlock) {
+        const int64_t r = r0 + i;
         const int64_t s = dup_row_slot(keys, v, o0, r, o1);
-        uint64_t active = ballot(s >= 0);
-        while (active) {
-            const int leader = __ffsll((unsigned long long)active) - 1;
-            const int64_t ls = __shfl(s, leader, kWave);
-            const uint64_t mask = ballot(s == ls) & active;
-            int64_t base = 0;
-            if (lane == leader)
-                base = (int64_t)atomicAdd((unsigned long long *)&v.slots[2 * ls + 1],
-                                          (unsigned long long)__popcll(mask));
-            base = __shfl(base, leader, kWave);
-            if ((mask >> lane) & 1ull)
-                v.grouped[base + mbcnt(mask)] = pay[r];
-            active &= ~mask;
+        int e = kRowSkip;
+        if (s >= 0) {
+            e = agg_insert(mkey, s);
+            if (e >= 0)
+                atomicAdd(&mcnt[e], 1u);
+            else
+                e = kRowDirect;
         }
+        rent[i] = (int16_t)e;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kAggMap; i += kBlock) {
+        if (mkey[i] != kAggNone)
+            mbase[i] = (int64_t)atomicAdd((unsigned long long *)&v.slots[2 * mkey[i] + 1],
+                                          (unsigned long long)mcnt[i]);
+        mcnt[i] = 0;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kAggRows; i += kBlock) {
+        const int e = rent[i];
+        if (e == kRowSkip)
+            continue;
+        const int64_t r = r0 + i;
+        int64_t at;
+        if (e >= 0) {
+            at = mbase[e] + (int64_t)atomicAdd(&mcnt[e], 1u);
+        } else {
+            const int64_t s = dup_row_slot(keys, v, o0, r, o1);
+            at = (int64_t)atomicAdd((unsigned long long *)&v.slots[2 * s + 1], 1ull);
+        }
+        v.grouped[at] = pay[r];
     }
 }
 
@@ -591,10 +710,16 @@ static int table_grid(int max_blocks)
 }
 
 template <typename K>
-hipError_t run_build(const K *keys, const int64_t *pay, const TView &v, int32_t *status,
-                     int max_blocks, hipStream_t s)
+hipError_t run_build(const K *keys, const int64_t *pay, const TView &v, int64_t rows,
+                     int32_t *status, int max_blocks, hipStream_t s)
 {
     const int G = table_grid(max_blocks);
+    // the grouping kernels' workgroups each take a fixed share of the rows
+    // (of the slots: 2 rows + 16 P)
+    const int64_t P = v.pe - v.pb;
+    const unsigned Gr = (unsigned)std::max<int64_t>(1, (rows + kAggRows - 1) / kAggRows);
+    const unsigned Gs = (unsigned)std::max<int64_t>(1, (2 * rows + 16 * P + kAllocSlots - 1) /
+                                                           kAllocSlots);
     trace_begin("tbl_init", s);
     hipLaunchKernelGGL(tbl_init, dim3(G), dim3(kBlock), 0, s, v);
     trace_end("tbl_init", s);
@@ -602,9 +727,15 @@ hipError_t run_build(const K *keys, const int64_t *pay, const TView &v, int32_t 
     hipLaunchKernelGGL((tbl_insert<K>), dim3(G), dim3(kBlock), 0, s, keys, pay, v, status);
     trace_end("tbl_insert", s);
     hipLaunchKernelGGL(grp_reset, dim3(G), dim3(kBlock), 0, s, v);
-    hipLaunchKernelGGL((grp_count<K>), dim3(G), dim3(kBlock), 0, s, keys, v);
-    hipLaunchKernelGGL(grp_alloc, dim3(G), dim3(kBlock), 0, s, v);
-    hipLaunchKernelGGL((grp_scatter<K>), dim3(G), dim3(kBlock), 0, s, keys, pay, v);
+    trace_begin("grp_count", s);
+    hipLaunchKernelGGL((grp_count<K>), dim3(Gr), dim3(kBlock), 0, s, keys, v);
+    trace_end("grp_count", s);
+    trace_begin("grp_alloc", s);
+    hipLaunchKernelGGL(grp_alloc, dim3(Gs), dim3(kBlock), 0, s, v);
+    trace_end("grp_alloc", s);
+    trace_begin("grp_scatter", s);
+    hipLaunchKernelGGL((grp_scatter<K>), dim3(Gr), dim3(kBlock), 0, s, keys, pay, v);
+    trace_end("grp_scatter", s);
     return hipGetLastError();
 }
 
@@ -618,8 +749,12 @@ hipError_t run_probe_group(const K *pk, const int64_t *pv, const TView &v, int g
     hipLaunchKernelGGL((probe_chain<K>), dim3(G), dim3(kBlock), 0, s, pk, pv, v, group, w, o,
                        status);
     trace_end("probe_chain", s);
+    // The expansion's work is the output rows, which can be millions for one
+    // probe row: it always gets a full device (it returns at once when no
+    // tile deferred rows).
     trace_begin("probe_expand", s);
-    hipLaunchKernelGGL((probe_expand<K>), dim3(G), dim3(kBlock), 0, s, pk, pv, v, group, w, o);
+    hipLaunchKernelGGL((probe_expand<K>), dim3(table_grid(0)), dim3(kBlock), 0, s, pk, pv, v,
+                       group, w, o);
     trace_end("probe_expand", s);
     return hipGetLastError();
 }
@@ -635,11 +770,11 @@ hipError_t launch_table_setup(const int64_t *off_in, int64_t n, int64_t *off_tab
 }
 
 hipError_t launch_build(const void *keys, const int64_t *pay, int key_bytes, const TView &v,
-                        int32_t *status, int max_blocks, hipStream_t s)
+                        int64_t rows, int32_t *status, int max_blocks, hipStream_t s)
 {
     if (key_bytes == 8)
-        return run_build<int64_t>((const int64_t *)keys, pay, v, status, max_blocks, s);
-    return run_build<int32_t>((const int32_t *)keys, pay, v, status, max_blocks, s);
+        return run_build<int64_t>((const int64_t *)keys, pay, v, rows, status, max_blocks, s);
+    return run_build<int32_t>((const int32_t *)keys, pay, v, rows, status, max_blocks, s);
 }
 
 hipError_t launch_fallback_setup(const int64_t *offAL, const int64_t *offAR, int stride,

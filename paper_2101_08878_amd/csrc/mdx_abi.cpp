@@ -167,8 +167,8 @@ int32_t mdx_trace_kernel(const char *kernel, hipEvent_t *h_starts, hipEvent_t *h
     }
     static const char *known[] = {"part_hist", "part_scatter", "tbl_init",
                                   "tbl_insert", "probe_chain", "probe_expand",
-                                  "seg_hist", "seg_scatter", "rj_join",
-                                  "transpose_sum"};
+                                  "seg_hist", "seg_scatter", "rj_join", "grp_count",
+                                  "grp_alloc", "grp_scatter", "transpose_sum"};
     bool ok = false;
     for (const char *k : known)
         ok |= std::string(k) == kernel;
@@ -403,7 +403,7 @@ int32_t mdx_join_build(const void *d_keys, const int64_t *d_payload, const int64
     hipError_t e = launch_table_setup(d_offsets, n, t.d_offsets, t.d_flags, t.d_bump, P, stream);
     if (e != hipSuccess)
         return hip_fail(e, W);
-    e = launch_build(d_keys, d_payload, key_type, make_view(t, t.d_offsets, 0, P), d_status, 0,
+    e = launch_build(d_keys, d_payload, key_type, make_view(t, t.d_offsets, 0, P), n, d_status, 0,
                      stream);
     if (e != hipSuccess)
         return hip_fail(e, W);
@@ -716,7 +716,7 @@ static hipError_t enqueue_merge(const mdx_merge_desc &d, void *d_ws, hipStream_t
     // return at once, and return sooner with fewer workgroups
     auto blocks = [](int64_t rows) { return (int)std::min<int64_t>((rows >> 14) + 1, 1 << 20); };
     if (e == hipSuccess)
-        e = launch_build(lk1, lv1, key_type, v, d_status, blocks(n_left), stream);
+        e = launch_build(lk1, lv1, key_type, v, n_left, d_status, blocks(n_left), stream);
     if (e == hipSuccess)
         e = launch_probe_group(rk1, rv1, key_type, P, v, 0, w, o, d_status, blocks(n_right),
                                stream);

@@ -362,11 +362,11 @@ int device_fill_blocks();
 void trace_begin(const char *kernel, hipStream_t s);
 void trace_end(const char *kernel, hipStream_t s);
 
-// Build a view: init slots, insert rows, group repeated keys.  The
-// grid-stride kernels of build and probe run on a full device, or on
+// Build a view of `rows` rows: init slots, insert rows, group repeated keys.
+// The grid-stride kernels of build and probe run on a full device, or on
 // max_blocks workgroups when 0 < max_blocks < that.
 hipError_t launch_build(const void *keys, const int64_t *pay, int key_bytes, const TView &v,
-                        int32_t *status, int max_blocks, hipStream_t s);
+                        int64_t rows, int32_t *status, int max_blocks, hipStream_t s);
 
 // Copy the build offsets (sanitized, for n build rows) into the table and
 // clear per-partition flags.  off_in may be null (flags only).

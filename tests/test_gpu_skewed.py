@@ -7,8 +7,12 @@ input: both partitions byte-exact, and the exact per-partition output
 counts from the count-only probe and from mdx_merge (which reports them
 even when its output does not fit).  Materialization is checked on the
 window L join R[0:m), m the longest prefix of right rows whose output stays
-within 2^24 rows; partitioning is stable, so the window is a prefix of every
-partition block."""
+within 2^28 rows (~2.7E8 rows, 6.4 GB): there by properties that fix the
+output exactly (every row's key equals the left and right keys its payloads
+name, every right row appears as often as the left table holds its key, no
+(left, right) pair twice, per-partition counts equal the oracle's); and the
+2^24-row window row by row against the oracle's materialized join.
+Partitioning is stable, so a window is a prefix of every partition block."""
 
 import numpy as np
 import pytest
@@ -16,6 +20,7 @@ import torch
 
 import oracle
 from tests.gpu_util import announce, assert_join_equals_oracle, dev, host, require_gpu, run_merge
+from tests.helpers import part_np
 from workloads import config_inputs
 
 pytestmark = pytest.mark.gpu
@@ -31,6 +36,14 @@ def skewed():
     kl, vl, kr, vr = config_inputs("skewed")
     ref = oracle.join(kl, vl, kr, vr, P=16, materialize=False)
     return kl, vl, kr, vr, ref
+
+
+@pytest.fixture(scope="module")
+def right_counts(skewed):
+    """For every right row, the output rows it makes (the left count of its
+    key), by the oracle."""
+    kl, _, kr, _, _ = skewed
+    return oracle.match_counts(kl, kr)
 
 
 def test_skewed_partition_build_count(skewed):
@@ -66,11 +79,45 @@ def test_skewed_merge_counts(skewed):
     assert got["status"] & mdx.MDX_DEV_OUTPUT_OVERFLOW
 
 
-def test_skewed_window_materialized(skewed):
-    announce("skewed window L x R[0:m)")
+def test_skewed_window_materialized(skewed, right_counts):
+    announce("skewed window L x R[0:m), 2^24 rows")
     kl, vl, kr, vr, _ = skewed
-    c = np.cumsum(oracle.match_counts(kl, kr))
+    c = np.cumsum(right_counts)
     m = int(np.searchsorted(c, 1 << 24, side="right"))
     assert 0 < m < kr.size
     got = run_merge(kl, vl, kr[:m], vr[:m], 16, cap=int(c[m - 1]))
     assert_join_equals_oracle(kl, vl, kr[:m], vr[:m], 16, got)
+
+
+def test_skewed_window_2_28(skewed, right_counts):
+    """The 2^28-row window of the workload's reading (~2.7E8 output rows)."""
+    import paper_2101_08878_amd as mdx
+    announce("skewed window L x R[0:m), 2^28 rows")
+    kl, vl, kr, vr, _ = skewed
+    cnt = right_counts
+    c = np.cumsum(cnt)
+    m = int(np.searchsorted(c, 1 << 28, side="right"))
+    total = int(c[m - 1])
+    assert 0 < m < kr.size and total > (1 << 27)
+    ref = oracle.join(kl, vl, kr[:m], vr[:m], P=16, materialize=False)
+    assert ref["total"] == total
+    lk, rk = dev(kl), dev(kr)
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ok, ol, orr, off = mdx.mdx_merge(lk, dev(vl), rk[:m], dev(vr[:m]), 16, out_capacity=total,
+                                     status=status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    assert np.array_equal(np.diff(host(off)), ref["per_part"])
+    # payloads are row indices: every row's key is the key of both rows it names
+    assert torch.equal(ok, lk[ol]) and torch.equal(ok, rk[orr])
+    # every right row appears exactly as often as the left table holds its key
+    assert torch.equal(torch.bincount(orr, minlength=m).cpu(), torch.from_numpy(cnt[:m]))
+    # and never with the same left row twice
+    pairs = torch.sort(orr * kl.size + ol).values
+    assert not bool((pairs[1:] == pairs[:-1]).any().item())
+    del pairs
+    # rows of block p belong to partition p (every 97th row)
+    o = host(off)
+    idx = np.arange(0, total, 97)
+    blocks = np.searchsorted(o, idx, side="right") - 1
+    assert np.array_equal(part_np(host(ok[torch.from_numpy(idx).cuda()]), 16), blocks)
