@@ -104,6 +104,10 @@ const char *mdx_last_error(void);
 /* ---------------------------------------------------------------------------
  * Hash partition (the local half of the shuffle).
  *
+ * Section V-B ("cuDF Merge", shuffle on): each worker splits its frame by a
+ * hash of the join key into one packed buffer per destination worker, the
+ * buffers Section IV-B's Isend/Irecv coroutines then ship as raw device
+ * memory.
  * Stable partition of one table by p = fmix64(key) mod P.  On return (once
  * the stream reaches it):
  *   d_offsets[0] = 0, d_offsets[P] = n, and destination p's rows occupy
@@ -154,6 +158,9 @@ int32_t mdx_hash_partition_noalloc(const void *d_keys, const int64_t *d_payload,
 /* ---------------------------------------------------------------------------
  * Join build: one hash table per partition of the build (left) table.
  *
+ * Section V-B ("cuDF Merge"): after the shuffle each worker merges the left
+ * and right rows it received for its key range; this is the build half of
+ * that inner hash join, over every destination partition at once.
  * The build input is a table partitioned by mdx_hash_partition (rows of
  * destination p in [d_offsets[p], d_offsets[p+1])).  The table memory
  * d_table_mem (caller-owned, at least mdx_join_table_bytes(n, P, key_type)
@@ -196,6 +203,9 @@ int32_t mdx_join_build(const void *d_keys, const int64_t *d_payload, const int64
  * Join probe: inner equi-join of a partitioned probe (right) table against a
  * built table, partition by partition.
  *
+ * Section V-B ("cuDF Merge"): the probe half of the worker's merge; the
+ * figure's "fraction match" is the share of right rows whose key occurs on
+ * the left.
  * Output rows are (key, left payload, right payload), one per pair of equal-
  * key rows (multiset semantics).  Partition p's output rows occupy
  * [d_out_offsets[p], d_out_offsets[p+1]); d_out_offsets [P+1] int64 is always
@@ -225,6 +235,10 @@ int32_t mdx_join_probe(const mdx_table *h_table, const void *d_keys, const int64
 /* ---------------------------------------------------------------------------
  * Merge: the whole per-worker path in one call.
  *
+ * Section V-B ("cuDF Merge") with Section IV-B's buffers: the hash shuffle's
+ * local partition of both frames followed by the merge of every partition,
+ * on raw device buffers (no serialization, as the paper's point-to-point
+ * layer sends them).
  * Partitions the left (build) and right (probe) tables into P destinations,
  * then joins every partition.  Inside the workspace each destination's rows
  * are further split by the top bits of the hash into sub-buckets small

@@ -257,21 +257,6 @@ __device__ __forceinline__ int agg_insert(int64_t *mkey, int64_t s)
     return -1;
 }
 
-// Entry of slot s if the map holds it, else -1 (the map is complete).
-__device__ __forceinline__ int agg_find(const int64_t *mkey, int64_t s)
-{
-    uint32_t h = agg_home(s);
-    for (int k = 0; k < kAggProbe; ++k) {
-        const int64_t cur = mkey[h];
-        if (cur == s)
-            return (int)h;
-        if (cur == kAggNone)
-            return -1;
-        h = (h + 1) & (kAggMap - 1);
-    }
-    return -1;
-}
-
 // Rows of workgroup b: [o0 + b kAggRows, ...) of the view's rows.
 __device__ __forceinline__ void agg_rows(const TView &v, int64_t &o0, int64_t &r0, int64_t &r1)
 {
