@@ -54,6 +54,10 @@ def parse():
     ap.add_argument("--budget-gb", type=float, default=200.0, help="serving: HBM budget")
     ap.add_argument("--graph-merges", type=int, default=256,
                     help="batched: merges captured per HIP graph (graphs replay in order)")
+    ap.add_argument("--fused-ws-gb", type=float, default=64.0,
+                    help="batched: workspace of the fused batch (more waves when smaller)")
+    ap.add_argument("--fused-tuning", default="table", choices=["table", "default"],
+                    help="batched: the fused batch's tuning (the autotuner's table, or defaults)")
     ap.add_argument("--cpu-baseline", default="on", choices=["on", "off", "full"],
                     help="on: one-thread oracle on a 0.2-scale sample + all-cores oracle at "
                          "full size; full: both at full size (the one-thread leg takes ~1 min)")
@@ -209,6 +213,48 @@ def batched_inputs(torch, specs, dev, seed=0, frac=0.3):
     return jobs, matched
 
 
+def fmix64_torch(torch, x):
+    """MurmurHash3's 64-bit finalizer on int64 tensors (wrapping products;
+    logical shifts by masking), for checking partitions of device output."""
+    m1 = 0xff51afd7ed558ccd - (1 << 64)
+    m2 = 0xc4ceb9fe1a85ec53 - (1 << 64)
+    x = x ^ ((x >> 33) & ((1 << 31) - 1))
+    x = x * m1
+    x = x ^ ((x >> 33) & ((1 << 31) - 1))
+    x = x * m2
+    return x ^ ((x >> 33) & ((1 << 31) - 1))
+
+
+def batch_rows_check(torch, jobs):
+    """Row-level check of every merge of a batch whose left keys are
+    distinct and whose payloads are row indices: every output row's key
+    equals the key of its left row and of its right row; the right rows of
+    the output are exactly the right rows whose key occurs on the left, each
+    once; every row of partition block p has fmix64(key) mod P = p (P a power
+    of two).  Together these fix the join's rows and per-partition offsets.
+    Returns a message for the first failing merge, or None."""
+    for i, j in enumerate(jobs):
+        P = j.P
+        assert P & (P - 1) == 0
+        off = j.out_offsets
+        n = int(off[-1])
+        kl, kr = j.left_keys.long(), j.right_keys.long()
+        k, lp, rp = j.out[0][:n].long(), j.out[1][:n], j.out[2][:n]
+        if n and not (bool((lp >= 0).all()) and bool((lp < kl.numel()).all())
+                      and bool((rp >= 0).all()) and bool((rp < kr.numel()).all())):
+            return f"merge {i}: payload out of range"
+        if n and not (torch.equal(kl[lp], k) and torch.equal(kr[rp], k)):
+            return f"merge {i}: a row's key differs from its left or right row's"
+        want = torch.nonzero(torch.isin(kr, kl)).flatten()
+        if not torch.equal(torch.sort(rp).values, want):
+            return f"merge {i}: the right rows of the output are not the matching ones, once each"
+        part = fmix64_torch(torch, k) & (P - 1)
+        block = torch.repeat_interleave(torch.arange(P, device=k.device), torch.diff(off))
+        if not torch.equal(part, block):
+            return f"merge {i}: a row outside its key's partition block"
+    return None
+
+
 def batched_cpu_baseline(specs, budget_s=15.0):
     """The oracle (one host thread) on the batch's first merges, drawn with
     the workloads generator, until budget_s of oracle time is spent."""
@@ -282,6 +328,12 @@ def run_batched(args):
             raise SystemExit(f"{label}: merge {bad[0]} gave |J|={tot[bad[0]]}, status {st[bad[0]]}, "
                              f"want {matched[bad[0]]}")
 
+    def check_rows(label):
+        bad = batch_rows_check(torch, jobs)
+        if bad:
+            raise SystemExit(f"{label}: {bad}")
+        log(f"  {label}: every row of all {len(jobs)} merges checked")
+
     def timed(fn, reps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
@@ -326,7 +378,60 @@ def run_batched(args):
     res["graph"] = (ms, wall)
     log(f"  batch in {len(graphs)} HIP graphs: {ms:.2f} ms device, {wall:.2f} ms wall, "
         f"{rows / (wall / 1e3):.4g} rows/s")
+    check_rows("graph")
+
+    # the fused batch: one launch per step for all merges, eager and as one
+    # HIP graph
+    tuning = "table" if args.fused_tuning == "table" else None
+    lo, hi = mdx.mdx_batch_workspace_bytes(jobs, tuning)
+    del graphs, ws
+    torch.cuda.empty_cache()
+    fb = mdx.FusedBatch(jobs, tuning=tuning,
+                        workspace_bytes=max(lo, min(hi, int(args.fused_ws_gb * 1e9))))
+    waves, launches = fb.info()
+    log(f"batched: fused batch, {waves} waves, {launches} launches per run, workspace "
+        f"{fb.workspace.numel() / 1e9:.1f} GB (one wave: {hi / 1e9:.1f} GB)")
+
+    def fused():
+        fb.run(stream)
+
+    for _ in range(max(args.warmup, 1)):
+        fused()
+    torch.cuda.synchronize()
+    for j in jobs:
+        j.out_offsets.fill_(-1)
+        for t in j.out:
+            t.fill_(-1)
+    fused()
+    torch.cuda.synchronize()
+    check("fused")
+    check_rows("fused")
+    ms, wall = timed(fused, args.steps)
+    res["fused"] = (ms, wall)
+    log(f"  fused batch: {ms:.2f} ms device, {wall:.2f} ms wall, {rows / (wall / 1e3):.4g} rows/s")
+    gf = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gf, stream=stream):
+        fb.run(stream)
+    torch.cuda.synchronize()
+
+    def fused_graph():
+        with torch.cuda.stream(stream):
+            gf.replay()
+
+    for j in jobs:
+        j.out_offsets.fill_(-1)
+    fused_graph()
+    torch.cuda.synchronize()
+    check("fused graph")
+    ms, wall = timed(fused_graph, args.steps)
+    res["fused graph"] = (ms, wall)
+    log(f"  fused batch in one HIP graph: {ms:.2f} ms device, {wall:.2f} ms wall, "
+        f"{rows / (wall / 1e3):.4g} rows/s")
+    del gf
+
     seq_wall = res["one merge at a time"][1]
+    lanes_wall = res["graph"][1]
+    wall = res["fused graph"][1]
     step_bytes = sum((s.n_left + s.n_right) * (2 * (4 if s.key_dtype == "int32" else 8) + 16)
                      + (s.n_left + s.n_right) * ((4 if s.key_dtype == "int32" else 8) + 8 + 16)
                      for s in specs) + sum(m * ((4 if s.key_dtype == "int32" else 8) + 16)
@@ -342,18 +447,25 @@ def run_batched(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int32/int64", "data": "synthetic",
         "config": {"workload": f"batched: {len(specs)} merges, {rows} input rows, P=8, "
-                               f"match fraction 0.3, {lanes} lanes, replayed from HIP graphs of "
-                               f"{args.graph_merges} merges",
-                   "merges": len(specs), "input_rows": rows, "lanes": lanes,
-                   "graph_merges": args.graph_merges},
+                               f"match fraction 0.3; fused batch (one launch per step, "
+                               f"{waves} waves, tuning {args.fused_tuning}) replayed from one "
+                               f"HIP graph",
+                   "merges": len(specs), "input_rows": rows, "waves": waves,
+                   "launches_per_run": launches, "tuning": args.fused_tuning,
+                   "lanes_path": f"{lanes} lanes, HIP graphs of {args.graph_merges} merges"},
         "roofline": {"bound": "hbm", "kernel": "whole batch", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None},
         "modes_ms": {k: {"device": round(v[0], 3), "wall": round(v[1], 3)} for k, v in res.items()},
         "speedup_vs_one_at_a_time": round(seq_wall / wall, 3),
+        "speedup_vs_lanes_graphs": round(lanes_wall / wall, 3),
+        "checked": "every output row of every merge (fused and lanes+graphs): keys equal on "
+                   "both sides, every right row whose key is on the left exactly once, rows in "
+                   "their key's partition",
     }
     if args.cpu_baseline == "on":
-        del jobs, ws, ws1
+        fb.close()
+        del jobs, ws1, fb
         line["cpu_baseline"] = batched_cpu_baseline(specs)
     print(json.dumps(line), flush=True)
 

@@ -58,7 +58,7 @@
 extern "C" {
 #endif
 
-#define MDX_ABI_VERSION 2
+#define MDX_ABI_VERSION 3
 
 /* Largest number of partitions (destinations). */
 #define MDX_MAX_P 4096
@@ -315,6 +315,77 @@ int32_t mdx_merge_batch_workspace_bytes(int32_t count, const mdx_merge_desc *h_d
 
 int32_t mdx_merge_batch(int32_t count, const mdx_merge_desc *h_descs, int32_t lanes, void *d_ws,
                         size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Fused batches: every step of many merges in one launch per step.
+ *
+ * For the same workload as mdx_merge_batch (Section V-B: a worker, or a
+ * service, with many merges of uneven sizes at once).  Instead of running
+ * whole merges side by side, a batch runs each step of the merge -- first
+ * partition pass, segmented pass, LDS join, output offsets -- once for all
+ * merges: one kernel launch per step covers every merge's tiles (merge m
+ * owns a range of the launch's workgroups, found from a prefix of the
+ * merges' block counts), and the join's workgroups take sub-buckets of all
+ * merges from one ticket counter.  A batch of thousands of merges is then
+ * about a dozen launches per wave instead of twenty per merge.
+ *
+ * Merge i computes the rows and offsets mdx_merge computes with the same
+ * descriptor (row order inside a partition is implementation-defined, as
+ * there), with one difference of method: a build sub-bucket too large for a
+ * workgroup's LDS table (heavily repeated keys) is joined in table-sized
+ * chunks by its workgroup instead of by the global-table join, so a batch
+ * never leaves the radix join.  That is exact for any input but slow when a
+ * few keys repeat very many times; mdx_merge handles such inputs better.
+ *
+ * Tuning (h_tuning: NULL, or one entry per merge): `fill` is the average
+ * build rows of a sub-bucket as a fraction of an LDS table (0: 0.8; else in
+ * [0.05, 1]); `fanout` caps the first pass's destinations (0: 128; else in
+ * [1, 4096]); `part_rows` picks the first pass's rows per thread, 2 or 8
+ * (0: by destinations; 8 needs at most 256 destinations, else 2 is used);
+ * `reserved` must be 0.  Tuning changes speed only, never results.
+ *
+ * Workspace: merges are packed, largest first within each key width, into
+ * waves whose workspace fits d_ws; waves run one after another.
+ * mdx_batch_workspace_bytes gives the least workspace that runs the batch
+ * (*h_min_bytes, waves of one merge at the worst) and the workspace that
+ * runs it as one wave (*h_all_bytes).
+ *
+ * mdx_batch_create checks every descriptor as mdx_merge would and plans the
+ * batch for d_ws (which must stay allocated and unused by others while the
+ * batch exists): the plan's device records are written into pinned host
+ * memory the batch owns (the one allocation here: host memory, none on the
+ * device).  mdx_batch_run enqueues on `stream` the copy of those records
+ * into d_ws followed by the launches; it can be captured into a HIP graph,
+ * whose replays then need the batch, d_ws and every merge's buffers alive
+ * and unchanged.  Runs of one batch must be ordered (they share d_ws).
+ * mdx_batch_info reports the waves and kernel launches of one run.
+ * Errors: MDX_ERR_INVALID for count < 0, a null h_descs with count > 0,
+ * bad tuning, a descriptor mdx_merge would reject (the message names the
+ * merge); MDX_ERR_WORKSPACE when d_ws is smaller than *h_min_bytes;
+ * MDX_ERR_HIP when the pinned allocation fails.
+ * ------------------------------------------------------------------------- */
+typedef struct mdx_batch_tuning {
+    float fill;
+    int32_t fanout;
+    int32_t part_rows;
+    int32_t reserved;
+} mdx_batch_tuning;
+
+typedef struct mdx_batch mdx_batch;
+
+int32_t mdx_batch_workspace_bytes(int32_t count, const mdx_merge_desc *h_descs,
+                                  const mdx_batch_tuning *h_tuning, size_t *h_min_bytes,
+                                  size_t *h_all_bytes);
+
+int32_t mdx_batch_create(int32_t count, const mdx_merge_desc *h_descs,
+                         const mdx_batch_tuning *h_tuning, void *d_ws, size_t ws_bytes,
+                         mdx_batch **h_batch);
+
+int32_t mdx_batch_info(const mdx_batch *batch, int32_t *h_waves, int32_t *h_launches);
+
+int32_t mdx_batch_run(mdx_batch *batch, hipStream_t stream);
+
+int32_t mdx_batch_destroy(mdx_batch *batch);
 
 /* ---------------------------------------------------------------------------
  * Serving: merge requests admitted as slots and memory free up.

@@ -64,6 +64,10 @@ class mdx_merge_desc(ctypes.Structure):
     ]
 
 
+class mdx_batch_tuning(ctypes.Structure):
+    _fields_ = [("fill", ctypes.c_float), ("fanout", _i32), ("part_rows", _i32), ("reserved", _i32)]
+
+
 class mdx_probe_desc(ctypes.Structure):
     _fields_ = [
         ("d_keys", _vp), ("d_payload", _vp), ("n", _i64),
@@ -100,6 +104,14 @@ _batch_ws = _sig("mdx_merge_batch_workspace_bytes", _i32, _i32, ctypes.POINTER(m
                  ctypes.POINTER(_sz))
 _batch = _sig("mdx_merge_batch", _i32, _i32, ctypes.POINTER(mdx_merge_desc), _i32, _vp, _sz, _vp)
 
+_fb_ws = _sig("mdx_batch_workspace_bytes", _i32, _i32, ctypes.POINTER(mdx_merge_desc),
+               ctypes.POINTER(mdx_batch_tuning), ctypes.POINTER(_sz), ctypes.POINTER(_sz))
+_fb_create = _sig("mdx_batch_create", _i32, _i32, ctypes.POINTER(mdx_merge_desc),
+                  ctypes.POINTER(mdx_batch_tuning), _vp, _sz, ctypes.POINTER(_vp))
+_fb_info = _sig("mdx_batch_info", _i32, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32))
+_fb_run = _sig("mdx_batch_run", _i32, _vp, _vp)
+_fb_destroy = _sig("mdx_batch_destroy", _i32, _vp)
+
 _srv_ws = _sig("mdx_server_workspace_bytes", _i32, _i32, _i64, _i64, _i32, ctypes.POINTER(_sz))
 _srv_create = _sig("mdx_server_create", _i32, _i32, _i64, _i64, _i32, _sz, _vp, _sz,
                    ctypes.POINTER(_vp))
@@ -122,6 +134,8 @@ ABI_FUNCTIONS = [
     "mdx_join_probe_workspace_bytes", "mdx_join_probe",
     "mdx_merge_workspace_bytes", "mdx_merge",
     "mdx_merge_batch_workspace_bytes", "mdx_merge_batch",
+    "mdx_batch_workspace_bytes", "mdx_batch_create", "mdx_batch_info", "mdx_batch_run",
+    "mdx_batch_destroy",
     "mdx_server_workspace_bytes", "mdx_server_create", "mdx_server_submit",
     "mdx_server_submit_probe", "mdx_server_poll",
     "mdx_server_stats", "mdx_server_destroy",
@@ -477,6 +491,103 @@ def mdx_merge_batch(jobs, *, lanes: int = 4, workspace=None, stream=None):
     _check(_batch(len(jobs), descs, int(lanes), _dev(workspace, "workspace"),
                   workspace.numel() * workspace.element_size(), _stream(stream)))
     return jobs
+
+
+# ---- fused batches ------------------------------------------------------------------------
+
+def _tunings(jobs, tuning):
+    """ctypes array of per-merge tuning, or None for the library defaults.
+    `tuning`: None, "table" (paper_2101_08878_amd/tuning.json by key width
+    and size), one dict for every merge, or a list of dicts (keys fill,
+    fanout, part_rows; missing keys mean the default)."""
+    if tuning is None or not jobs:
+        return None
+    if tuning == "table":
+        from .autotune import lookup
+        per = [lookup(j.left_keys.element_size(), max(j.left_keys.numel(), j.right_keys.numel()))
+               for j in jobs]
+    elif isinstance(tuning, dict):
+        per = [tuning] * len(jobs)
+    else:
+        per = list(tuning)
+        if len(per) != len(jobs):
+            raise ValueError("one tuning entry per merge")
+    arr = (mdx_batch_tuning * len(jobs))()
+    for i, t in enumerate(per):
+        arr[i].fill = float(t.get("fill", 0.0))
+        arr[i].fanout = int(t.get("fanout", 0))
+        arr[i].part_rows = int(t.get("part_rows", 0))
+    return arr
+
+
+def mdx_batch_workspace_bytes(jobs, tuning=None):
+    """(least, one-wave) workspace bytes of a fused batch of these jobs."""
+    lo, hi = _sz(0), _sz(0)
+    _check(_fb_ws(len(jobs), _batch_descs(jobs, False), _tunings(jobs, tuning), ctypes.byref(lo),
+                  ctypes.byref(hi)))
+    return int(lo.value), int(hi.value)
+
+
+class FusedBatch:
+    """A fused batch (mdx_batch_*): every merge's steps in one launch per
+    step.  Plans the jobs once (outputs missing from a job and the workspace
+    are allocated here); run() enqueues the batch and may be called again or
+    captured into a HIP graph.  The object keeps the jobs' tensors and the
+    workspace alive; close() (or garbage collection) frees the plan after
+    the caller has synchronized with every run."""
+
+    def __init__(self, jobs, *, tuning=None, workspace=None, workspace_bytes: int | None = None):
+        self.jobs = list(jobs)
+        made = []
+        for j in self.jobs:
+            dev = j.left_keys.device
+            if j.out is None:
+                j.out = _outputs(j.out_capacity, j.left_keys.dtype, dev, None)
+                made += list(j.out)
+            if j.out_offsets is None:
+                j.out_offsets = torch.empty(j.P + 1, dtype=torch.int64, device=dev)
+                made.append(j.out_offsets)
+        self._tuning = _tunings(self.jobs, tuning)
+        lo, hi = mdx_batch_workspace_bytes(self.jobs, tuning)
+        if workspace is None:
+            need = hi if workspace_bytes is None else max(lo, min(hi, int(workspace_bytes)))
+            dev = self.jobs[0].left_keys.device if self.jobs else torch.device("cuda")
+            workspace = _workspace(need, dev)
+            made.append(workspace)
+        self.workspace = workspace
+        self._made = made
+        self._handed = False
+        descs = _batch_descs(self.jobs, True)
+        h = _vp()
+        _check(_fb_create(len(self.jobs), descs, self._tuning, _dev(workspace, "workspace"),
+                          workspace.numel() * workspace.element_size(), ctypes.byref(h)))
+        self._h = h
+
+    def info(self):
+        """(waves, kernel launches) of one run."""
+        w, n = _i32(0), _i32(0)
+        _check(_fb_info(self._h, ctypes.byref(w), ctypes.byref(n)))
+        return int(w.value), int(n.value)
+
+    def run(self, stream=None):
+        if self._h is None:
+            raise MdxError(MDX_ERR_INVALID, "batch is closed")
+        if not self._handed:
+            _handoff(stream, self._made)
+            self._handed = True
+        _check(_fb_run(self._h, _stream(stream)))
+        return self.jobs
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            _check(_fb_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---- serving ------------------------------------------------------------------------------

@@ -1,8 +1,11 @@
 // The extern "C" entry points of libmdx: argument validation (pure host code,
 // before anything is enqueued), workspace and table carving, and the order of
 // kernel launches.  No device memory is allocated here.
+#include <string.h>
+
 #include <algorithm>
 #include <atomic>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -506,10 +509,12 @@ struct MergePlan {
     int qbits, q1bits, q2bits;
 };
 
-MergePlan merge_plan(int64_t nL, int64_t nR, int32_t P)
+// fill: average rows of the larger side per sub-bucket, as a fraction of a
+// table; fanout: the first pass's largest number of destinations.
+MergePlan merge_plan(int64_t nL, int64_t nR, int32_t P, double fill = kJoinFill, int fanout = 128)
 {
     MergePlan m;
-    const double per = kJoinFill * kJoinCap;
+    const double per = fill * kJoinCap;
     const double want = (double)std::max(nL, nR) / ((double)P * per);
     m.qbits = want <= 1.0 ? 0 : ceil_log2((int64_t)(want + 0.999999));
     // keep the sub-bucket count bounded; oversized sub-buckets fall back to
@@ -518,7 +523,7 @@ MergePlan merge_plan(int64_t nL, int64_t nR, int32_t P)
         --m.qbits;
     for (;; --m.qbits) {
         m.q1bits = 0;
-        while (m.q1bits < m.qbits && (P << (m.q1bits + 1)) <= 128)
+        while (m.q1bits < m.qbits && ((int64_t)P << (m.q1bits + 1)) <= fanout)
             ++m.q1bits;
         m.q2bits = m.qbits - m.q1bits;
         while (m.q2bits > 8) {  // the segmented pass splits at most 256 ways
@@ -928,6 +933,430 @@ int32_t mdx_merge_batch(int32_t count, const mdx_merge_desc *h_descs, int32_t la
             (void)hipEventDestroy(fork);
     }
     return e == hipSuccess ? MDX_OK : hip_fail(e, W);
+}
+
+// ---- fused batches: one launch per step for all merges --------------------------------
+
+}  // extern "C"
+
+namespace {
+
+// Per-unit block prefixes, one array of M + 1 entries per step.
+enum BatchStep { kTiles, kScan, kOffs, kSegPlan, kSegHist, kSegScan, kSegTiles, kSubs, kSteps };
+constexpr int64_t kUnitMaxBlocks = (int64_t)1 << 30;  // per step and unit (grid limit 2^31 - 1)
+
+struct Tuned {
+    double fill;
+    int fanout, rows;
+};
+
+int32_t check_tuning(const mdx_batch_tuning *h, int32_t i, Tuned *out, const char *W)
+{
+    const mdx_batch_tuning t = h ? h[i] : mdx_batch_tuning{0.0f, 0, 0, 0};
+    const std::string Wi = std::string(W) + " (merge " + std::to_string(i) + ")";
+    if (t.reserved != 0)
+        return fail(MDX_ERR_INVALID, Wi + ": tuning.reserved must be 0");
+    if (!(t.fill == 0.0f || (t.fill >= 0.05f && t.fill <= 1.0f)))
+        return fail(MDX_ERR_INVALID, Wi + ": tuning.fill outside {0} or [0.05, 1]");
+    if (t.fanout < 0 || t.fanout > MDX_MAX_P)
+        return fail(MDX_ERR_INVALID, Wi + ": tuning.fanout outside [0, MDX_MAX_P]");
+    if (t.part_rows != 0 && t.part_rows != 2 && t.part_rows != 8)
+        return fail(MDX_ERR_INVALID, Wi + ": tuning.part_rows not 0, 2 or 8");
+    out->fill = t.fill == 0.0f ? kJoinFill : (double)t.fill;
+    out->fanout = t.fanout ? t.fanout : 128;
+    out->rows = t.part_rows;
+    return MDX_OK;
+}
+
+// One merge of a fused batch: its plan and the layout of its workspace
+// (offsets from `base`, its place in d_ws).
+struct FusedMerge {
+    int32_t idx = 0;
+    MergePlan plan = {};
+    int64_t nA = 0, S = 0;
+    int R = 0, kt = 0, wave = 0;
+    PartLayout pl = {}, pr = {};
+    SegLayout sl = {}, sr = {};
+    size_t partL = 0, partR = 0, lk1 = 0, lv1 = 0, rk1 = 0, rv1 = 0, offAL = 0, offAR = 0,
+           digL = 0, digR = 0, segL = 0, segR = 0, lk2 = 0, lv2 = 0, rk2 = 0, rv2 = 0, subL = 0,
+           subR = 0, jst = 0, jbase = 0, bytes = 0, base = 0;
+    int64_t blocks[kSteps] = {};
+};
+
+FusedMerge fused_merge(const mdx_merge_desc &d, int32_t idx, const Tuned &t)
+{
+    FusedMerge F;
+    F.idx = idx;
+    F.kt = d.key_type;
+    F.plan = merge_plan(d.n_left, d.n_right, d.P, t.fill, t.fanout);
+    F.nA = (int64_t)d.P << F.plan.q1bits;
+    F.S = (int64_t)d.P << F.plan.qbits;
+    const int deflt = part_rows_per_thread((int32_t)F.nA);
+    F.R = t.rows == 2 ? kPartRowsLarge
+                      : (t.rows == 8 ? (F.nA <= kPartSmallMaxP ? kPartRowsSmall : kPartRowsLarge)
+                                     : deflt);
+    F.pl = part_layout(d.n_left, (int32_t)F.nA, F.R);
+    F.pr = part_layout(d.n_right, (int32_t)F.nA, F.R);
+    const bool two = F.plan.q2bits > 0;
+    if (two) {
+        F.sl = seg_layout(d.n_left, F.nA, F.plan.q2bits);
+        F.sr = seg_layout(d.n_right, F.nA, F.plan.q2bits);
+    }
+    const size_t kL = (size_t)(d.n_left > 0 ? d.n_left : 1),
+                 kR = (size_t)(d.n_right > 0 ? d.n_right : 1), kt = (size_t)d.key_type;
+    size_t o = 0;
+    auto take = [&](size_t &field, size_t bytes) {
+        field = o;
+        o += align_up(bytes);
+    };
+    take(F.partL, F.pl.bytes);
+    take(F.partR, F.pr.bytes);
+    take(F.lk1, kL * kt);
+    take(F.lv1, kL * 8);
+    take(F.rk1, kR * kt);
+    take(F.rv1, kR * 8);
+    take(F.offAL, (size_t)(F.nA + 1) * 8);
+    take(F.offAR, (size_t)(F.nA + 1) * 8);
+    take(F.digL, two ? kL + 4 : 0);
+    take(F.digR, two ? kR + 4 : 0);
+    take(F.segL, two ? F.sl.bytes : 0);
+    take(F.segR, two ? F.sr.bytes : 0);
+    take(F.lk2, two ? kL * kt : 0);
+    take(F.lv2, two ? kL * 8 : 0);
+    take(F.rk2, two ? kR * kt : 0);
+    take(F.rv2, two ? kR * 8 : 0);
+    take(F.subL, two ? (size_t)(F.S + 1) * 8 : 0);
+    take(F.subR, two ? (size_t)(F.S + 1) * 8 : 0);
+    take(F.jst, (size_t)F.S * 8);
+    take(F.jbase, (size_t)F.S * 8);
+    F.bytes = o;
+    F.blocks[kTiles] = F.pl.ntiles + F.pr.ntiles;
+    F.blocks[kScan] = 2 * F.nA;
+    F.blocks[kOffs] = 2;
+    F.blocks[kSegPlan] = two ? 2 : 0;
+    F.blocks[kSegHist] = two ? F.sl.max_chunks + F.sr.max_chunks : 0;
+    F.blocks[kSegScan] = two ? 2 * F.nA : 0;
+    F.blocks[kSegTiles] = two ? F.sl.max_tiles + F.sr.max_tiles : 0;
+    F.blocks[kSubs] = F.S;
+    return F;
+}
+
+// Bytes of the records one merge adds to the plan image, and a bound on the
+// image: records, block prefixes (M + 1 entries per step and unit) and the
+// 16-byte alignment of every array, with at most one unit per merge.
+size_t merge_record_bytes()
+{
+    return align_up(part_rec_bytes(), 16) + align_up(seg_rec_bytes(), 16) +
+           align_up(sizeof(JoinRec), 16);
+}
+
+size_t image_bound(int32_t count)
+{
+    const size_t c = (size_t)count;
+    return c * merge_record_bytes() + (size_t)kSteps * 4 * (2 * c) + c * (3 + kSteps) * 16;
+}
+
+// d_ws: [plan image][ticket per unit][waves]
+size_t fixed_bytes(int32_t count)
+{
+    return align_up(image_bound(count)) + align_up((size_t)(count > 0 ? count : 1) * 4);
+}
+
+// Merges of one key width and tile shape within one wave.
+struct BatchUnit {
+    int kt = 0, R = 0, maxD = 1, maxbits = 0;
+    bool dig = false;
+    std::vector<int32_t> merges;  // indexes into the FusedMerge list
+    int64_t total[kSteps] = {};
+    size_t part_off = 0, seg_off = 0, join_off = 0, pre_off[kSteps] = {}, ticket_off = 0;
+};
+
+int32_t check_fused(int32_t count, const mdx_merge_desc *h, const mdx_batch_tuning *t,
+                    std::vector<FusedMerge> *out, const char *W)
+{
+    if (count < 0)
+        return fail(MDX_ERR_INVALID, std::string(W) + ": count < 0");
+    if (count > 0 && !h)
+        return fail(MDX_ERR_INVALID, std::string(W) + ": h_descs is null");
+    out->clear();
+    out->reserve((size_t)count);
+    for (int32_t i = 0; i < count; ++i) {
+        const std::string Wi = std::string(W) + " (merge " + std::to_string(i) + ")";
+        if (int32_t e = check_sizes(h[i].n_left, h[i].P, h[i].key_type, Wi.c_str()))
+            return e;
+        if (int32_t e = check_sizes(h[i].n_right, h[i].P, h[i].key_type, Wi.c_str()))
+            return e;
+        Tuned tu;
+        if (int32_t e = check_tuning(t, i, &tu, W))
+            return e;
+        out->push_back(fused_merge(h[i], i, tu));
+    }
+    return MDX_OK;
+}
+
+}  // namespace
+
+struct mdx_batch {
+    int device = 0;
+    char *d_ws = nullptr;
+    size_t image_bytes = 0;
+    char *h_image = nullptr;  // pinned
+    std::vector<BatchUnit> units;
+    int32_t waves = 0, launches = 0;
+};
+
+extern "C" {
+
+int32_t mdx_batch_workspace_bytes(int32_t count, const mdx_merge_desc *h_descs,
+                                  const mdx_batch_tuning *h_tuning, size_t *h_min_bytes,
+                                  size_t *h_all_bytes)
+{
+    g_err.clear();
+    const char *W = "mdx_batch_workspace_bytes";
+    std::vector<FusedMerge> F;
+    if (int32_t e = check_fused(count, h_descs, h_tuning, &F, W))
+        return e;
+    if (!h_min_bytes || !h_all_bytes)
+        return fail(MDX_ERR_INVALID, std::string(W) + ": null output pointer");
+    size_t most = 0, all = 0;
+    for (const FusedMerge &f : F) {
+        most = std::max(most, align_up(f.bytes));
+        all += align_up(f.bytes);
+    }
+    *h_min_bytes = fixed_bytes(count) + most;
+    *h_all_bytes = fixed_bytes(count) + all;
+    return MDX_OK;
+}
+
+int32_t mdx_batch_create(int32_t count, const mdx_merge_desc *h_descs,
+                         const mdx_batch_tuning *h_tuning, void *d_ws, size_t ws_bytes,
+                         mdx_batch **h_batch)
+{
+    g_err.clear();
+    const char *W = "mdx_batch_create";
+    if (!h_batch)
+        return fail(MDX_ERR_INVALID, std::string(W) + ": h_batch is null");
+    *h_batch = nullptr;
+    std::vector<FusedMerge> F;
+    if (int32_t e = check_fused(count, h_descs, h_tuning, &F, W))
+        return e;
+    if (!d_ws || !aligned(d_ws, kAlign))
+        return fail(MDX_ERR_INVALID, std::string(W) + ": workspace null or not 256-byte aligned");
+    const size_t fixed = fixed_bytes(count);
+    size_t most = 0;
+    for (const FusedMerge &f : F)
+        most = std::max(most, align_up(f.bytes));
+    if (ws_bytes < fixed + most)
+        return fail(MDX_ERR_WORKSPACE,
+                    std::string(W) + ": workspace needs at least " + std::to_string(fixed + most) +
+                        " bytes");
+    for (int32_t i = 0; i < count; ++i) {
+        const std::string Wi = std::string(W) + " (merge " + std::to_string(i) + ")";
+        if (int32_t e = check_merge(h_descs[i], Wi.c_str()))
+            return e;
+        if (int32_t e = check_merge_ws(h_descs[i], d_ws, ws_bytes, 0, Wi.c_str()))
+            return e;
+    }
+
+    // Waves: merges of one key width and tile shape together, largest first;
+    // a wave takes merges until the next does not fit.
+    std::vector<int32_t> order((size_t)count);
+    for (int32_t i = 0; i < count; ++i)
+        order[(size_t)i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        const FusedMerge &x = F[(size_t)a], &y = F[(size_t)b];
+        if (x.kt != y.kt)
+            return x.kt > y.kt;
+        if (x.R != y.R)
+            return x.R > y.R;
+        return x.bytes > y.bytes;
+    });
+    std::unique_ptr<mdx_batch> B(new mdx_batch);
+    const size_t cap = ws_bytes - fixed;
+    size_t used = 0;
+    int wave = 0;
+    for (size_t k = 0; k < order.size(); ++k) {
+        FusedMerge &f = F[(size_t)order[k]];
+        const size_t b = align_up(f.bytes);
+        if (k > 0 && used + b > cap) {
+            ++wave;
+            used = 0;
+        }
+        f.wave = wave;
+        f.base = fixed + used;
+        used += b;
+        // a unit holds one key width and tile shape of one wave, within the
+        // grid limits
+        BatchUnit *u = B->units.empty() ? nullptr : &B->units.back();
+        bool fresh = !u || u->kt != f.kt || u->R != f.R ||
+                     F[(size_t)u->merges.back()].wave != f.wave;
+        for (int st = 0; st < kSteps && !fresh; ++st)
+            fresh = u->total[st] + f.blocks[st] > kUnitMaxBlocks;
+        if (fresh) {
+            B->units.emplace_back();
+            u = &B->units.back();
+            u->kt = f.kt;
+            u->R = f.R;
+        }
+        u->merges.push_back(order[k]);
+        for (int st = 0; st < kSteps; ++st)
+            u->total[st] += f.blocks[st];
+        u->maxD = std::max<int>(u->maxD, (int)f.nA);
+        u->maxbits = std::max(u->maxbits, f.plan.q2bits);
+        u->dig = u->dig || f.plan.q2bits > 0;
+    }
+    B->waves = count > 0 ? wave + 1 : 0;
+
+    // The plan image: per unit its records and block prefixes.
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += align_up(bytes, 16);
+        return at;
+    };
+    const size_t tickets = align_up(image_bound(count));
+    for (size_t ui = 0; ui < B->units.size(); ++ui) {
+        BatchUnit &u = B->units[ui];
+        const size_t M = u.merges.size();
+        u.part_off = take(M * part_rec_bytes());
+        u.seg_off = take(M * seg_rec_bytes());
+        u.join_off = take(M * sizeof(JoinRec));
+        for (int st = 0; st < kSteps; ++st)
+            u.pre_off[st] = take((M + 1) * 4);
+        u.ticket_off = tickets + ui * 4;
+    }
+    B->image_bytes = o;
+    if (o > image_bound(count))
+        return fail(MDX_ERR_INVALID, std::string(W) + ": internal plan size");  // cannot happen
+    if (o > 0) {
+        hipError_t e = hipHostMalloc((void **)&B->h_image, o, hipHostMallocDefault);
+        if (e != hipSuccess)
+            return hip_fail(e, W);
+        memset(B->h_image, 0, o);
+    }
+    char *ws = (char *)d_ws;
+    for (BatchUnit &u : B->units) {
+        std::vector<uint32_t> pre[kSteps];
+        for (int st = 0; st < kSteps; ++st)
+            pre[st].assign(1, 0u);
+        for (size_t j = 0; j < u.merges.size(); ++j) {
+            const FusedMerge &f = F[(size_t)u.merges[j]];
+            const mdx_merge_desc &d = h_descs[f.idx];
+            char *b = ws + f.base;
+            const bool two = f.plan.q2bits > 0;
+            uint8_t *digL = two ? (uint8_t *)(b + f.digL) : nullptr;
+            uint8_t *digR = two ? (uint8_t *)(b + f.digR) : nullptr;
+            int64_t *offAL = (int64_t *)(b + f.offAL), *offAR = (int64_t *)(b + f.offAR);
+            const PartArgs pt[2] = {
+                {d.d_left_keys, d.d_left_payload, d.n_left, b + f.lk1, (int64_t *)(b + f.lv1),
+                 offAL, digL, b + f.partL},
+                {d.d_right_keys, d.d_right_payload, d.n_right, b + f.rk1, (int64_t *)(b + f.rv1),
+                 offAR, digR, b + f.partR}};
+            part_rec(pt, f.kt, d.P, f.plan.q1bits, f.R, f.plan.q1bits, f.plan.q2bits,
+                     B->h_image + u.part_off + j * part_rec_bytes());
+            JoinRec jr = {};
+            if (two) {
+                const SegArgs sa[2] = {
+                    {b + f.lk1, (int64_t *)(b + f.lv1), digL, d.n_left, offAL, b + f.lk2,
+                     (int64_t *)(b + f.lv2), (int64_t *)(b + f.subL), b + f.segL},
+                    {b + f.rk1, (int64_t *)(b + f.rv1), digR, d.n_right, offAR, b + f.rk2,
+                     (int64_t *)(b + f.rv2), (int64_t *)(b + f.subR), b + f.segR}};
+                seg_rec(sa, f.kt, f.nA, f.plan.q1bits, f.plan.q2bits,
+                        B->h_image + u.seg_off + j * seg_rec_bytes());
+                jr.lk = b + f.lk2;
+                jr.lv = (const int64_t *)(b + f.lv2);
+                jr.subL = (const int64_t *)(b + f.subL);
+                jr.rk = b + f.rk2;
+                jr.rv = (const int64_t *)(b + f.rv2);
+                jr.subR = (const int64_t *)(b + f.subR);
+            } else {
+                jr.lk = b + f.lk1;
+                jr.lv = (const int64_t *)(b + f.lv1);
+                jr.subL = offAL;
+                jr.rk = b + f.rk1;
+                jr.rv = (const int64_t *)(b + f.rv1);
+                jr.subR = offAR;
+            }
+            jr.jstatus = (uint64_t *)(b + f.jst);
+            jr.jbase = (int64_t *)(b + f.jbase);
+            jr.S = f.S;
+            jr.o.key = d.d_out_key;
+            jr.o.lpay = d.d_out_lpay;
+            jr.o.rpay = d.d_out_rpay;
+            jr.o.cap = d.out_capacity;
+            jr.o.offsets = d.d_out_offsets;
+            jr.status = d.d_status;
+            jr.P = d.P;
+            jr.qbits = f.plan.qbits;
+            memcpy(B->h_image + u.join_off + j * sizeof(JoinRec), &jr, sizeof(jr));
+            for (int st = 0; st < kSteps; ++st)
+                pre[st].push_back(pre[st].back() + (uint32_t)f.blocks[st]);
+        }
+        for (int st = 0; st < kSteps; ++st)
+            memcpy(B->h_image + u.pre_off[st], pre[st].data(), pre[st].size() * 4);
+    }
+    int launches = B->image_bytes > 0 ? 1 : 0;
+    for (const BatchUnit &u : B->units)
+        launches += 4 + (u.total[kSegPlan] > 0 ? 4 : 0) + 3;
+    B->launches = launches;
+    B->d_ws = ws;
+    (void)hipGetDevice(&B->device);
+    *h_batch = B.release();
+    return MDX_OK;
+}
+
+int32_t mdx_batch_info(const mdx_batch *batch, int32_t *h_waves, int32_t *h_launches)
+{
+    g_err.clear();
+    if (!batch || !h_waves || !h_launches)
+        return fail(MDX_ERR_INVALID, "mdx_batch_info: null argument");
+    *h_waves = batch->waves;
+    *h_launches = batch->launches;
+    return MDX_OK;
+}
+
+int32_t mdx_batch_run(mdx_batch *batch, hipStream_t stream)
+{
+    g_err.clear();
+    const char *W = "mdx_batch_run";
+    if (!batch)
+        return fail(MDX_ERR_INVALID, std::string(W) + ": batch is null");
+    if (batch->units.empty())
+        return MDX_OK;
+    char *img = batch->d_ws;
+    hipError_t e = hipMemcpyAsync(img, batch->h_image, batch->image_bytes, hipMemcpyHostToDevice,
+                                  stream);
+    for (const BatchUnit &u : batch->units) {
+        if (e != hipSuccess)
+            break;
+        const int M = (int)u.merges.size();
+        auto stage = [&](int st) {
+            return BatchStage{(const uint32_t *)(img + u.pre_off[st]), (uint32_t)u.total[st]};
+        };
+        e = launch_partition_batch(img + u.part_off, M, u.kt, u.R, u.maxD, u.dig, stage(kTiles),
+                                   stage(kScan), stage(kOffs), stream);
+        if (e == hipSuccess && u.total[kSegPlan] > 0)
+            e = launch_seg_batch(img + u.seg_off, M, u.kt, u.maxbits, stage(kSegPlan),
+                                 stage(kSegHist), stage(kSegScan), stage(kSegTiles), stream);
+        if (e == hipSuccess)
+            e = launch_rjoin_batch((const JoinRec *)(img + u.join_off), M,
+                                   (const uint32_t *)(img + u.pre_off[kSubs]),
+                                   (uint32_t)u.total[kSubs], (uint32_t *)(img + u.ticket_off), u.kt,
+                                   stream);
+    }
+    return e == hipSuccess ? MDX_OK : hip_fail(e, W);
+}
+
+int32_t mdx_batch_destroy(mdx_batch *batch)
+{
+    g_err.clear();
+    if (!batch)
+        return MDX_OK;
+    hipError_t e = hipSuccess;
+    if (batch->h_image)
+        e = hipHostFree(batch->h_image);
+    delete batch;
+    return e == hipSuccess ? MDX_OK : hip_fail(e, "mdx_batch_destroy");
 }
 
 // ---- serving: merges admitted as slots and memory free up ------------------------------

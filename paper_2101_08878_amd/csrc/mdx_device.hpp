@@ -217,6 +217,27 @@ __device__ __forceinline__ int upper_index(const int64_t *a, int lo, int hi, int
     return l;
 }
 
+// Range of a batch launch that holds block x: the last m in [0, M) with
+// pre[m] <= x, for non-decreasing pre[0..M] with pre[0] = 0 <= x < pre[M]
+// (merge m owns blocks [pre[m], pre[m+1]); merges with no blocks are
+// skipped).  Called by whole waves with the same x: each round compares 64
+// entries spread over the remaining range, so M <= 4096 takes two rounds.
+__device__ inline int find_range(const uint32_t *pre, int M, uint32_t x)
+{
+    const int lane = lane_id();
+    int lo = 0, span = M;  // the answer lies in [lo, lo + span)
+    while (span > 1) {
+        const int step = (span + kWave - 1) / kWave;
+        const int off = lane * step;
+        const bool ok = off < span && pre[lo + off] <= x;
+        const uint64_t b = ballot(ok);  // lane 0 holds: pre[lo] <= x
+        const int j = b ? 63 - __builtin_clzll(b) : 0;
+        lo += j * step;
+        span = step < span - j * step ? step : span - j * step;
+    }
+    return lo;
+}
+
 // ---- chained scan over ordered tiles (decoupled look-back) -------------------
 // Status word of a tile: flag in the top 2 bits (1: its own count is
 // published, 2: its inclusive prefix is published), value below.

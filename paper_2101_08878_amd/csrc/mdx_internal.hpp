@@ -59,10 +59,11 @@ struct PartLayout {
     size_t cnt_off, totals_off, bytes;
 };
 
-inline PartLayout part_layout(int64_t n, int32_t P)
+// R: rows per thread of the tiles (0: part_rows_per_thread(P)).
+inline PartLayout part_layout(int64_t n, int32_t P, int R = 0)
 {
     PartLayout L;
-    L.rows_per_thread = part_rows_per_thread(P);
+    L.rows_per_thread = R > 0 ? R : part_rows_per_thread(P);
     const int64_t tile = (int64_t)kBlock * L.rows_per_thread;
     L.ntiles = (n + tile - 1) / tile;
     size_t o = 0;
@@ -155,6 +156,38 @@ struct SegArgs {
 // set of launches.
 hipError_t launch_seg_partition(const SegArgs *tables, int ntables, int key_bytes, int64_t nseg,
                                 int shift, int bits, hipStream_t s);
+
+// ---- batch launches -------------------------------------------------------------
+// One launch of a step covers many merges: merge m owns blocks
+// [pre[m], pre[m+1]) of the grid (pre in device memory, M + 1 entries,
+// pre[M] = blocks) and reads its arguments from record m of a device array
+// of records written on the host by the *_rec functions.
+struct BatchStage {
+    const uint32_t *pre;
+    uint32_t blocks;
+};
+
+// Record of a merge's first pass over its two tables (tables[0] build,
+// tables[1] probe) with tiles of kBlock R rows, as launch_partition would
+// run it; part_rec_bytes() bytes.
+size_t part_rec_bytes();
+void part_rec(const PartArgs *tables, int key_bytes, int32_t P, int sbits, int R, int dshift,
+              int dbits, void *dst);
+// Record of a merge's segmented pass, as launch_seg_partition would run it.
+size_t seg_rec_bytes();
+void seg_rec(const SegArgs *tables, int key_bytes, int64_t nseg, int shift, int bits, void *dst);
+
+// First pass of M merges of one key width and rows per thread R: `tiles`
+// (both tables' tiles per merge), `scan` (2 D per merge), `offs` (2 per
+// merge).  maxD: the largest destination count; dig: some merge writes
+// digit bytes.
+hipError_t launch_partition_batch(const void *recs, int M, int key_bytes, int R, int maxD, bool dig,
+                                  BatchStage tiles, BatchStage scan, BatchStage offs, hipStream_t s);
+// Segmented pass of the merges that have one (others own no blocks): `plan`
+// (2 per merge), `hist` (max_chunks of both tables), `scan` (2 nseg),
+// `tiles` (max_tiles of both tables); maxbits: the largest digit width.
+hipError_t launch_seg_batch(const void *recs, int M, int key_bytes, int maxbits, BatchStage plan,
+                            BatchStage hist, BatchStage scan, BatchStage tiles, hipStream_t s);
 
 // ---- radix join (LDS tables per sub-bucket) ---------------------------------
 // Sub-bucket s of S = P 2^qbits holds build rows [subL[s], subL[s+1]) and
@@ -400,6 +433,30 @@ hipError_t launch_rjoin(const void *lk, const int64_t *lv, const int64_t *subL, 
                         const int64_t *rv, const int64_t *subR, int key_bytes, int32_t P,
                         int qbits, const RJoinWs &w, const ProbeOut &o, int32_t *status,
                         hipStream_t s);
+// Radix join of every merge of a batch (one key width): record m describes
+// merge m (its S sub-buckets, its chained scan jstatus/jbase of S entries,
+// output); Spre [M + 1] prefix of the merges' S in device memory, S its
+// total; ticket: a device counter.  Clears the chained scans, joins (a build
+// sub-bucket larger than an LDS table is joined in table-sized chunks), and
+// writes every merge's output offsets.
+struct JoinRec {
+    const void *lk;
+    const int64_t *lv;
+    const int64_t *subL;  // [S + 1]
+    const void *rk;
+    const int64_t *rv;
+    const int64_t *subR;  // [S + 1]
+    uint64_t *jstatus;    // [S]
+    int64_t *jbase;       // [S]
+    int64_t S;
+    ProbeOut o;
+    int32_t *status;
+    int32_t P, qbits;
+};
+
+hipError_t launch_rjoin_batch(const JoinRec *recs, int M, const uint32_t *Spre, uint32_t S,
+                              uint32_t *ticket, int key_bytes, hipStream_t s);
+
 // A merge's output offsets: the radix join's when it ran, else (pw non-null)
 // the global-table probe's.
 hipError_t launch_merge_finalize(int32_t P, int qbits, const RJoinWs &w, const ProbeWs *pw,

@@ -20,6 +20,8 @@
 // A merge runs each step once for its two tables, and splits every bucket
 // again with the segmented pass below (seg_*), whose histogram counts digit
 // bytes the first scatter wrote beside its rows.
+#include <string.h>
+
 #include "mdx_internal.hpp"
 
 namespace mdx {
@@ -68,20 +70,15 @@ __device__ __forceinline__ PartTable<K> pick(const PartPair<K> &T, bool second)
     return r;
 }
 
+// Counts of tile `tile` of table tb per destination into tb.cnt.
 template <typename K, int R>
-__global__ __launch_bounds__(kBlock) void part_hist(PartPair<K> T, Dest d)
+__device__ __forceinline__ void hist_tile(const PartTable<K> &tb, int64_t tile, const Dest &d,
+                                          uint32_t *hist)
 {
-    extern __shared__ uint32_t hist[];
     const int tid = threadIdx.x;
     const int P = d.ndest;  // destinations
     for (int p = tid; p < P; p += kBlock)
         hist[p] = 0;
-    // XCD-contiguous tile order: the counts of neighbouring tiles share cache
-    // lines, which then fill in one L2
-    const int64_t g = tile_of_block(blockIdx.x, gridDim.x);
-    const bool second = g >= T.t[0].ntiles;
-    const PartTable<K> tb = pick(T, second);
-    const int64_t tile = second ? g - T.t[0].ntiles : g;
     const int64_t row0 = tile * (int64_t)(kBlock * R);
     // Keys are read 16 bytes per lane when the column is 16-byte aligned
     // (the counts do not depend on which thread reads which row).
@@ -133,6 +130,17 @@ __global__ __launch_bounds__(kBlock) void part_hist(PartPair<K> T, Dest d)
         tb.cnt[(int64_t)p * tb.ntiles + tile] = hist[p];
 }
 
+template <typename K, int R>
+__global__ __launch_bounds__(kBlock) void part_hist(PartPair<K> T, Dest d)
+{
+    extern __shared__ uint32_t hist[];
+    // XCD-contiguous tile order: the counts of neighbouring tiles share cache
+    // lines, which then fill in one L2
+    const int64_t g = tile_of_block(blockIdx.x, gridDim.x);
+    const bool second = g >= T.t[0].ntiles;
+    hist_tile<K, R>(pick(T, second), second ? g - T.t[0].ntiles : g, d, hist);
+}
+
 // Block p: exclusive prefix of cnt[p][0..ntiles) in place, total to totals[p].
 // Rounds of kBlock * kScanV counts: loaded and stored with consecutive lanes
 // on consecutive counts, staged in LDS so that thread t sums the kScanV
@@ -146,19 +154,13 @@ __device__ __forceinline__ int scan_slot(int e)
     return e + e / kScanV;
 }
 
-// Block b: destination b mod D of table b / D.
-__global__ __launch_bounds__(kBlock) void part_scan_tiles(int64_t *cnt0, int64_t ntiles0,
-                                                          int64_t *totals0, int64_t *cnt1,
-                                                          int64_t ntiles1, int64_t *totals1, int D)
+// Destination p of one table: prefix of its row of counts, total to totals[p].
+__device__ __forceinline__ void scan_tiles_of(int64_t *cnt, int64_t ntiles, int64_t *totals, int p)
 {
     __shared__ int64_t scratch[kWavesPerBlock];
     __shared__ int64_t buf[kScanChunk + kBlock];
     const int tid = threadIdx.x;
-    const bool second = (int)blockIdx.x >= D;
-    const int p = second ? (int)blockIdx.x - D : (int)blockIdx.x;
-    const int64_t ntiles = second ? ntiles1 : ntiles0;
-    int64_t *totals = second ? totals1 : totals0;
-    int64_t *row = (second ? cnt1 : cnt0) + (int64_t)p * ntiles;
+    int64_t *row = cnt + (int64_t)p * ntiles;
     int64_t carry = 0;
     for (int64_t base = 0; base < ntiles; base += kScanChunk) {
         const int m = (int)(ntiles - base < kScanChunk ? ntiles - base : kScanChunk);
@@ -195,13 +197,20 @@ __global__ __launch_bounds__(kBlock) void part_scan_tiles(int64_t *cnt0, int64_t
         totals[p] = carry;
 }
 
-// Block t: table t's destination offsets.
-__global__ __launch_bounds__(kBlock) void part_offsets(const int64_t *totals0, int64_t *off0,
-                                                       const int64_t *totals1, int64_t *off1, int P)
+// Block b: destination b mod D of table b / D.
+__global__ __launch_bounds__(kBlock) void part_scan_tiles(int64_t *cnt0, int64_t ntiles0,
+                                                          int64_t *totals0, int64_t *cnt1,
+                                                          int64_t ntiles1, int64_t *totals1, int D)
+{
+    const bool second = (int)blockIdx.x >= D;
+    scan_tiles_of(second ? cnt1 : cnt0, second ? ntiles1 : ntiles0, second ? totals1 : totals0,
+                  second ? (int)blockIdx.x - D : (int)blockIdx.x);
+}
+
+// One table's destination offsets from its totals.
+__device__ __forceinline__ void offsets_of(const int64_t *totals, int64_t *off, int P)
 {
     __shared__ int64_t scratch[kWavesPerBlock];
-    const int64_t *totals = blockIdx.x ? totals1 : totals0;
-    int64_t *off = blockIdx.x ? off1 : off0;
     int64_t carry = 0;
     for (int base = 0; base < P; base += kBlock) {
         const int p = base + threadIdx.x;
@@ -214,6 +223,13 @@ __global__ __launch_bounds__(kBlock) void part_offsets(const int64_t *totals0, i
     }
     if (threadIdx.x == 0)
         off[P] = carry;
+}
+
+// Block t: table t's destination offsets.
+__global__ __launch_bounds__(kBlock) void part_offsets(const int64_t *totals0, int64_t *off0,
+                                                       const int64_t *totals1, int64_t *off1, int P)
+{
+    offsets_of(blockIdx.x ? totals1 : totals0, blockIdx.x ? off1 : off0, P);
 }
 
 // LDS carve-up of part_scatter (bytes, 16-byte aligned pieces).
@@ -398,19 +414,27 @@ __device__ __forceinline__ void scatter_tile(const K *__restrict__ keys,
     }
 }
 
+// First-pass scatter of tile `tile` of table tb.
+template <typename K, int R, bool DIG>
+__device__ __forceinline__ void part_scatter_tile(const PartTable<K> &tb, int64_t tile,
+                                                  const Dest &d, int dshift, int dbits,
+                                                  unsigned char *smem)
+{
+    scatter_tile<K, R, DIG>(
+        tb.keys, tb.pay, tile * (int64_t)(kBlock * R), tb.n, d.ndest, d.nbits,
+        [&](uint64_t h) { return dest_of(h, d); },
+        [&](int p) { return tb.off[p] + tb.cnt[(int64_t)p * tb.ntiles + tile]; }, tb.keys_out,
+        tb.pay_out, smem, tb.dig, dshift, dbits);
+}
+
 template <typename K, int R, bool DIG>
 __global__ __launch_bounds__(kBlock) void part_scatter(PartPair<K> T, Dest d, int dshift, int dbits)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int64_t g = tile_of_block(blockIdx.x, gridDim.x);
     const bool second = g >= T.t[0].ntiles;
-    const PartTable<K> tb = pick(T, second);
-    const int64_t tile = second ? g - T.t[0].ntiles : g;
-    scatter_tile<K, R, DIG>(
-        tb.keys, tb.pay, tile * (int64_t)(kBlock * R), tb.n, d.ndest, d.nbits,
-        [&](uint64_t h) { return dest_of(h, d); },
-        [&](int p) { return tb.off[p] + tb.cnt[(int64_t)p * tb.ntiles + tile]; }, tb.keys_out,
-        tb.pay_out, smem, tb.dig, dshift, dbits);
+    part_scatter_tile<K, R, DIG>(pick(T, second), second ? g - T.t[0].ntiles : g, d, dshift,
+                                 dbits, smem);
 }
 
 // ---- segmented partition -------------------------------------------------------
@@ -470,10 +494,9 @@ __device__ __forceinline__ SegTable<K> pick(const SegPair<K> &T, bool second)
 // segment of every chunk (a chunk then finds its segment with one load
 // instead of a search over the starts; seg_scan writes the same for tiles).
 template <typename K>
-__global__ __launch_bounds__(kBlock) void seg_plan(SegPair<K> T, int nseg)
+__device__ __forceinline__ void seg_plan_of(const SegTable<K> &tb, int nseg)
 {
     __shared__ int64_t scratch[kWavesPerBlock];
-    const SegTable<K> tb = pick(T, blockIdx.x != 0);
     int64_t tcarry = 0, ccarry = 0;
     for (int base = 0; base < nseg; base += kBlock) {
         const int a = base + threadIdx.x;
@@ -499,6 +522,12 @@ __global__ __launch_bounds__(kBlock) void seg_plan(SegPair<K> T, int nseg)
     }
 }
 
+template <typename K>
+__global__ __launch_bounds__(kBlock) void seg_plan(SegPair<K> T, int nseg)
+{
+    seg_plan_of(pick(T, blockIdx.x != 0), nseg);
+}
+
 // Block = chunk (the first table's max_chunks blocks, then the second's):
 // per-tile digit counts, stored as the exclusive prefix over the chunk's
 // earlier tiles; chunk totals to csum.  The digits are the bytes the first
@@ -506,13 +535,10 @@ __global__ __launch_bounds__(kBlock) void seg_plan(SegPair<K> T, int nseg)
 // instead of the key.  All of the chunk's bytes are loaded at once, four
 // per load, then counted into one LDS histogram per tile.
 template <typename K>
-__global__ __launch_bounds__(kBlock) void seg_hist(SegPair<K> T, int nseg, int bits)
+__device__ __forceinline__ void seg_hist_chunk(const SegTable<K> &tb, int64_t c, int nseg, int bits)
 {
     __shared__ uint32_t hist[kSegChunkTiles][kSegMaxDest];
     static_assert(kSegTile == 4096, "tile of a row: (r - r0) >> 12");
-    const bool second = (int64_t)blockIdx.x >= T.t[0].max_chunks;
-    const SegTable<K> tb = pick(T, second);
-    const int64_t c = second ? (int64_t)blockIdx.x - T.t[0].max_chunks : (int64_t)blockIdx.x;
     const int64_t nchunks = tb.chunk_start[nseg];
     const int a = (int)tb.chunk_seg[c];  // meaningful when c < nchunks
     if (c >= nchunks)
@@ -560,17 +586,23 @@ __global__ __launch_bounds__(kBlock) void seg_hist(SegPair<K> T, int nseg, int b
     }
 }
 
+template <typename K>
+__global__ __launch_bounds__(kBlock) void seg_hist(SegPair<K> T, int nseg, int bits)
+{
+    const bool second = (int64_t)blockIdx.x >= T.t[0].max_chunks;
+    seg_hist_chunk(pick(T, second),
+                   second ? (int64_t)blockIdx.x - T.t[0].max_chunks : (int64_t)blockIdx.x, nseg,
+                   bits);
+}
+
 // Block = segment (nseg blocks per table): chunk totals -> exclusive prefix
 // over the segment's chunks (in place); destination bases outoff[a D + q];
 // the segment of each of the segment's tiles.
 template <typename K>
-__global__ __launch_bounds__(kBlock) void seg_scan(SegPair<K> T, int nseg, int bits)
+__device__ __forceinline__ void seg_scan_of(const SegTable<K> &tb, int a, int nseg, int bits)
 {
     __shared__ int64_t scratch[kWavesPerBlock];
     __shared__ int64_t tot[kSegMaxDest];
-    const bool second = (int)blockIdx.x >= nseg;
-    const SegTable<K> tb = pick(T, second);
-    const int a = second ? (int)blockIdx.x - nseg : (int)blockIdx.x;
     const int D = 1 << bits, tid = threadIdx.x;
     for (int64_t t = tb.tile_start[a] + tid; t < tb.tile_start[a + 1]; t += kBlock)
         tb.tile_seg[t] = (uint32_t)a;
@@ -599,16 +631,19 @@ __global__ __launch_bounds__(kBlock) void seg_scan(SegPair<K> T, int nseg, int b
         tb.outoff[(int64_t)nseg * D] = tb.segoff[nseg];
 }
 
+template <typename K>
+__global__ __launch_bounds__(kBlock) void seg_scan(SegPair<K> T, int nseg, int bits)
+{
+    const bool second = (int)blockIdx.x >= nseg;
+    seg_scan_of(pick(T, second), second ? (int)blockIdx.x - nseg : (int)blockIdx.x, nseg, bits);
+}
+
 // Block = tile (the first table's max_tiles, then the second's, in
 // XCD-contiguous order over both).
 template <typename K>
-__global__ __launch_bounds__(kBlock) void seg_scatter(SegPair<K> T, int nseg, int shift, int bits)
+__device__ __forceinline__ void seg_scatter_tile(const SegTable<K> &tb, int64_t t, int nseg,
+                                                 int shift, int bits, unsigned char *smem)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int64_t g = tile_of_block(blockIdx.x, gridDim.x);
-    const bool second = g >= T.t[0].max_tiles;
-    const SegTable<K> tb = pick(T, second);
-    const int64_t t = second ? g - T.t[0].max_tiles : g;
     const int64_t ntiles = tb.tile_start[nseg];
     const int a = (int)tb.tile_seg[t];  // meaningful when t < ntiles
     if (t >= ntiles)
@@ -628,16 +663,23 @@ __global__ __launch_bounds__(kBlock) void seg_scatter(SegPair<K> T, int nseg, in
         tb.keys_out, tb.pay_out, smem, nullptr, 0, 0);
 }
 
-template <typename K, int R>
-hipError_t run_partition(const PartArgs *tables, int ntables, int32_t P, int sbits, int dshift,
-                         int dbits, hipStream_t s)
+template <typename K>
+__global__ __launch_bounds__(kBlock) void seg_scatter(SegPair<K> T, int nseg, int shift, int bits)
 {
-    const Dest d = make_dest(P, sbits);
-    const int D = d.ndest;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int64_t g = tile_of_block(blockIdx.x, gridDim.x);
+    const bool second = g >= T.t[0].max_tiles;
+    seg_scatter_tile(pick(T, second), second ? g - T.t[0].max_tiles : g, nseg, shift, bits, smem);
+}
+
+// Kernel view of 1 or 2 tables partitioned into D destinations.
+template <typename K>
+PartPair<K> part_pair(const PartArgs *tables, int ntables, int D, int R)
+{
     PartPair<K> T = {};
     for (int i = 0; i < ntables; ++i) {
         const PartArgs &a = tables[i];
-        const PartLayout L = part_layout(a.n, D);
+        const PartLayout L = part_layout(a.n, D, R);
         PartTable<K> &t = T.t[i];
         t.keys = (const K *)a.keys;
         t.pay = a.pay;
@@ -650,6 +692,16 @@ hipError_t run_partition(const PartArgs *tables, int ntables, int32_t P, int sbi
         t.cnt = (int64_t *)((char *)a.ws + L.cnt_off);
         t.totals = (int64_t *)((char *)a.ws + L.totals_off);
     }
+    return T;
+}
+
+template <typename K, int R>
+hipError_t run_partition(const PartArgs *tables, int ntables, int32_t P, int sbits, int dshift,
+                         int dbits, hipStream_t s)
+{
+    const Dest d = make_dest(P, sbits);
+    const int D = d.ndest;
+    const PartPair<K> T = part_pair<K>(tables, ntables, D, R);
     const int64_t tiles = T.t[0].ntiles + T.t[1].ntiles;
     if (tiles > 0) {
         trace_begin("part_hist", s);
@@ -685,9 +737,9 @@ hipError_t run_partition(const PartArgs *tables, int ntables, int32_t P, int sbi
     return hipGetLastError();
 }
 
+// Kernel view of 1 or 2 tables split into nseg segments of 2^bits.
 template <typename K>
-hipError_t run_seg_partition(const SegArgs *tables, int ntables, int64_t nseg, int shift,
-                             int bits, hipStream_t s)
+SegPair<K> seg_pair(const SegArgs *tables, int ntables, int64_t nseg, int bits)
 {
     SegPair<K> T = {};
     for (int i = 0; i < ntables; ++i) {
@@ -711,6 +763,14 @@ hipError_t run_seg_partition(const SegArgs *tables, int ntables, int64_t nseg, i
         t.max_tiles = L.max_tiles;
         t.max_chunks = L.max_chunks;
     }
+    return T;
+}
+
+template <typename K>
+hipError_t run_seg_partition(const SegArgs *tables, int ntables, int64_t nseg, int shift,
+                             int bits, hipStream_t s)
+{
+    const SegPair<K> T = seg_pair<K>(tables, ntables, nseg, bits);
     const int ns = (int)nseg;
     const size_t lds = scatter_lds(kSegTile, 1 << bits, (int)sizeof(K), false).total;
     if (lds > kMaxLdsBytes)
@@ -731,6 +791,206 @@ hipError_t run_seg_partition(const SegArgs *tables, int ntables, int64_t nseg, i
                        dim3(kBlock), lds, s, T, ns, shift, bits);
     trace_end("seg_scatter", s);
     return hipGetLastError();
+}
+
+// ---- batches: one launch per step for many merges -----------------------------
+// A batch launch covers every merge of a batch: merge m owns the blocks
+// [pre[m], pre[m+1]) of the step's grid and reads its tables from record m
+// (device memory).  The bodies are the ones the single launches run.
+template <typename K>
+struct PartRec {
+    PartPair<K> T;  // build table, probe table
+    Dest d;
+    int32_t dshift, dbits;
+};
+
+template <typename K>
+struct SegRec {
+    SegPair<K> T;
+    int32_t nseg, shift, bits, pad;
+};
+
+template <typename K, int R>
+__global__ __launch_bounds__(kBlock) void part_hist_batch(const PartRec<K> *__restrict__ B,
+                                                          const uint32_t *__restrict__ pre, int M)
+{
+    extern __shared__ uint32_t hist[];
+    const uint32_t g = (uint32_t)tile_of_block(blockIdx.x, gridDim.x);
+    const int m = find_range(pre, M, g);
+    const PartRec<K> &r = B[m];
+    const int64_t b = (int64_t)(g - pre[m]);
+    const int second = b >= r.T.t[0].ntiles;
+    hist_tile<K, R>(r.T.t[second], second ? b - r.T.t[0].ntiles : b, r.d, hist);
+}
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void part_scan_batch(const PartRec<K> *__restrict__ B,
+                                                          const uint32_t *__restrict__ pre, int M)
+{
+    const int m = find_range(pre, M, blockIdx.x);
+    const PartRec<K> &r = B[m];
+    const int b = (int)(blockIdx.x - pre[m]), D = r.d.ndest;
+    const int second = b >= D;
+    const PartTable<K> &t = r.T.t[second];
+    scan_tiles_of(t.cnt, t.ntiles, t.totals, second ? b - D : b);
+}
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void part_offsets_batch(const PartRec<K> *__restrict__ B,
+                                                             const uint32_t *__restrict__ pre,
+                                                             int M)
+{
+    const int m = find_range(pre, M, blockIdx.x);
+    const PartRec<K> &r = B[m];
+    const PartTable<K> &t = r.T.t[blockIdx.x - pre[m]];
+    offsets_of(t.totals, t.off, r.d.ndest);
+}
+
+template <typename K, int R>
+__global__ __launch_bounds__(kBlock) void part_scatter_batch(const PartRec<K> *__restrict__ B,
+                                                             const uint32_t *__restrict__ pre,
+                                                             int M)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t g = (uint32_t)tile_of_block(blockIdx.x, gridDim.x);
+    const int m = find_range(pre, M, g);
+    const PartRec<K> &r = B[m];
+    const int64_t b = (int64_t)(g - pre[m]);
+    const int second = b >= r.T.t[0].ntiles;
+    const PartTable<K> &t = r.T.t[second];
+    const int64_t tile = second ? b - r.T.t[0].ntiles : b;
+    if (t.dig)
+        part_scatter_tile<K, R, true>(t, tile, r.d, r.dshift, r.dbits, smem);
+    else
+        part_scatter_tile<K, R, false>(t, tile, r.d, r.dshift, r.dbits, smem);
+}
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void seg_plan_batch(const SegRec<K> *__restrict__ B,
+                                                         const uint32_t *__restrict__ pre, int M)
+{
+    const int m = find_range(pre, M, blockIdx.x);
+    const SegRec<K> &r = B[m];
+    seg_plan_of(r.T.t[blockIdx.x - pre[m]], r.nseg);
+}
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void seg_hist_batch(const SegRec<K> *__restrict__ B,
+                                                         const uint32_t *__restrict__ pre, int M)
+{
+    const int m = find_range(pre, M, blockIdx.x);
+    const SegRec<K> &r = B[m];
+    const int64_t b = (int64_t)(blockIdx.x - pre[m]);
+    const int second = b >= r.T.t[0].max_chunks;
+    seg_hist_chunk(r.T.t[second], second ? b - r.T.t[0].max_chunks : b, r.nseg, r.bits);
+}
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void seg_scan_batch(const SegRec<K> *__restrict__ B,
+                                                         const uint32_t *__restrict__ pre, int M)
+{
+    const int m = find_range(pre, M, blockIdx.x);
+    const SegRec<K> &r = B[m];
+    const int b = (int)(blockIdx.x - pre[m]);
+    const int second = b >= r.nseg;
+    seg_scan_of(r.T.t[second], second ? b - r.nseg : b, r.nseg, r.bits);
+}
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void seg_scatter_batch(const SegRec<K> *__restrict__ B,
+                                                            const uint32_t *__restrict__ pre,
+                                                            int M)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t g = (uint32_t)tile_of_block(blockIdx.x, gridDim.x);
+    const int m = find_range(pre, M, g);
+    const SegRec<K> &r = B[m];
+    const int64_t b = (int64_t)(g - pre[m]);
+    const int second = b >= r.T.t[0].max_tiles;
+    seg_scatter_tile(r.T.t[second], second ? b - r.T.t[0].max_tiles : b, r.nseg, r.shift, r.bits,
+                     smem);
+}
+
+template <typename K, int R>
+hipError_t run_partition_batch(const void *recs, int M, int maxD, bool dig, BatchStage tiles,
+                               BatchStage scan, BatchStage offs, hipStream_t s)
+{
+    const PartRec<K> *B = (const PartRec<K> *)recs;
+    if (tiles.blocks > 0) {
+        trace_begin("part_hist", s);
+        hipLaunchKernelGGL((part_hist_batch<K, R>), dim3(tiles.blocks), dim3(kBlock),
+                           (size_t)maxD * sizeof(uint32_t), s, B, tiles.pre, M);
+        trace_end("part_hist", s);
+    }
+    if (scan.blocks > 0)
+        hipLaunchKernelGGL(part_scan_batch<K>, dim3(scan.blocks), dim3(kBlock), 0, s, B, scan.pre,
+                           M);
+    if (offs.blocks > 0)
+        hipLaunchKernelGGL(part_offsets_batch<K>, dim3(offs.blocks), dim3(kBlock), 0, s, B,
+                           offs.pre, M);
+    if (tiles.blocks > 0) {
+        const size_t lds = scatter_lds(kBlock * R, maxD, (int)sizeof(K), dig).total;
+        if (lds > kMaxLdsBytes)
+            return hipErrorInvalidValue;
+        hipError_t e = hipFuncSetAttribute((const void *)part_scatter_batch<K, R>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess)
+            return e;
+        trace_begin("part_scatter", s);
+        hipLaunchKernelGGL((part_scatter_batch<K, R>), dim3(tiles.blocks), dim3(kBlock), lds, s, B,
+                           tiles.pre, M);
+        trace_end("part_scatter", s);
+    }
+    return hipGetLastError();
+}
+
+template <typename K>
+hipError_t run_seg_batch(const void *recs, int M, int maxbits, BatchStage plan, BatchStage hist,
+                         BatchStage scan, BatchStage tiles, hipStream_t s)
+{
+    const SegRec<K> *B = (const SegRec<K> *)recs;
+    if (plan.blocks == 0)
+        return hipSuccess;
+    const size_t lds = scatter_lds(kSegTile, 1 << maxbits, (int)sizeof(K), false).total;
+    if (lds > kMaxLdsBytes)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(seg_plan_batch<K>, dim3(plan.blocks), dim3(kBlock), 0, s, B, plan.pre, M);
+    trace_begin("seg_hist", s);
+    hipLaunchKernelGGL(seg_hist_batch<K>, dim3(hist.blocks), dim3(kBlock), 0, s, B, hist.pre, M);
+    trace_end("seg_hist", s);
+    hipLaunchKernelGGL(seg_scan_batch<K>, dim3(scan.blocks), dim3(kBlock), 0, s, B, scan.pre, M);
+    hipError_t e = hipFuncSetAttribute((const void *)seg_scatter_batch<K>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess)
+        return e;
+    trace_begin("seg_scatter", s);
+    hipLaunchKernelGGL(seg_scatter_batch<K>, dim3(tiles.blocks), dim3(kBlock), lds, s, B,
+                       tiles.pre, M);
+    trace_end("seg_scatter", s);
+    return hipGetLastError();
+}
+
+template <typename K>
+void write_part_rec(const PartArgs *tables, int32_t P, int sbits, int R, int dshift, int dbits,
+                    void *dst)
+{
+    PartRec<K> r = {};
+    r.d = make_dest(P, sbits);
+    r.T = part_pair<K>(tables, 2, r.d.ndest, R);
+    r.dshift = dshift;
+    r.dbits = dbits;
+    memcpy(dst, &r, sizeof(r));
+}
+
+template <typename K>
+void write_seg_rec(const SegArgs *tables, int64_t nseg, int shift, int bits, void *dst)
+{
+    SegRec<K> r = {};
+    r.T = seg_pair<K>(tables, 2, nseg, bits);
+    r.nseg = (int32_t)nseg;
+    r.shift = shift;
+    r.bits = bits;
+    memcpy(dst, &r, sizeof(r));
 }
 
 }  // namespace
@@ -760,6 +1020,67 @@ hipError_t launch_seg_partition(const SegArgs *tables, int ntables, int key_byte
     if (key_bytes == 8)
         return run_seg_partition<int64_t>(tables, ntables, nseg, shift, bits, s);
     return run_seg_partition<int32_t>(tables, ntables, nseg, shift, bits, s);
+}
+
+}  // namespace mdx
+
+namespace mdx {
+
+size_t part_rec_bytes()
+{
+    static_assert(sizeof(PartRec<int32_t>) == sizeof(PartRec<int64_t>), "one record size");
+    return sizeof(PartRec<int64_t>);
+}
+
+size_t seg_rec_bytes()
+{
+    static_assert(sizeof(SegRec<int32_t>) == sizeof(SegRec<int64_t>), "one record size");
+    return sizeof(SegRec<int64_t>);
+}
+
+void part_rec(const PartArgs *tables, int key_bytes, int32_t P, int sbits, int R, int dshift,
+              int dbits, void *dst)
+{
+    if (key_bytes == 8)
+        write_part_rec<int64_t>(tables, P, sbits, R, dshift, dbits, dst);
+    else
+        write_part_rec<int32_t>(tables, P, sbits, R, dshift, dbits, dst);
+}
+
+void seg_rec(const SegArgs *tables, int key_bytes, int64_t nseg, int shift, int bits, void *dst)
+{
+    if (key_bytes == 8)
+        write_seg_rec<int64_t>(tables, nseg, shift, bits, dst);
+    else
+        write_seg_rec<int32_t>(tables, nseg, shift, bits, dst);
+}
+
+hipError_t launch_partition_batch(const void *recs, int M, int key_bytes, int R, int maxD, bool dig,
+                                  BatchStage tiles, BatchStage scan, BatchStage offs, hipStream_t s)
+{
+    if (R == kPartRowsSmall) {
+        if (maxD > kPartSmallMaxP)
+            return hipErrorInvalidValue;
+        return key_bytes == 8
+                   ? run_partition_batch<int64_t, kPartRowsSmall>(recs, M, maxD, dig, tiles, scan,
+                                                                  offs, s)
+                   : run_partition_batch<int32_t, kPartRowsSmall>(recs, M, maxD, dig, tiles, scan,
+                                                                  offs, s);
+    }
+    if (R != kPartRowsLarge)
+        return hipErrorInvalidValue;
+    return key_bytes == 8
+               ? run_partition_batch<int64_t, kPartRowsLarge>(recs, M, maxD, dig, tiles, scan, offs, s)
+               : run_partition_batch<int32_t, kPartRowsLarge>(recs, M, maxD, dig, tiles, scan, offs,
+                                                              s);
+}
+
+hipError_t launch_seg_batch(const void *recs, int M, int key_bytes, int maxbits, BatchStage plan,
+                            BatchStage hist, BatchStage scan, BatchStage tiles, hipStream_t s)
+{
+    return key_bytes == 8
+               ? run_seg_batch<int64_t>(recs, M, maxbits, plan, hist, scan, tiles, s)
+               : run_seg_batch<int32_t>(recs, M, maxbits, plan, hist, scan, tiles, s);
 }
 
 }  // namespace mdx

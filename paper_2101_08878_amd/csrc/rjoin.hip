@@ -273,9 +273,236 @@ __device__ __forceinline__ void emit_batch(const K *kk, const int64_t *vv, const
     }
 }
 
+// Insert build rows [b0, b0 + n) (0 < n <= kJoinCap) into the LDS table,
+// kBuildBatch rows per thread at a time.  Rows past n load the last row (no
+// branch per load) and are not inserted.
+template <typename K>
+__device__ __forceinline__ void build_table(const K *__restrict__ lk,
+                                            const int64_t *__restrict__ lv, int64_t b0, int64_t n,
+                                            int64_t *tkey, int64_t *tp, uint16_t *tn,
+                                            uint32_t *head)
+{
+    const int tid = threadIdx.x;
+    for (int i = tid; i < kJoinHeads; i += kJoinThreads)
+        head[i] = kSent;
+    __syncthreads();
+    const K *kb = lk + b0;
+    const int64_t *vb = lv + b0;
+    const uint32_t last = (uint32_t)n - 1;
+    for (int base = 0; base < (int)n; base += kBuildBatch * kJoinThreads) {
+        K bk[kBuildBatch];
+        int64_t bv[kBuildBatch];
+#pragma unroll
+        for (int j = 0; j < kBuildBatch; ++j) {
+            uint32_t i = (uint32_t)(base + j * kJoinThreads) + tid;
+            i = i < last ? i : last;
+            bk[j] = __builtin_nontemporal_load(kb + i);
+            bv[j] = __builtin_nontemporal_load(vb + i);
+        }
+#pragma unroll
+        for (int j = 0; j < kBuildBatch; ++j) {
+            const int i = base + j * kJoinThreads + tid;
+            if (i < n) {
+                const int64_t k = (int64_t)bk[j];
+                tkey[i] = k;
+                tp[i] = bv[j];
+                tn[i] = (uint16_t)atomicExch(&head[bucket_of(k)], (uint32_t)i);
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// The LDS of a join workgroup.
+struct JoinLds {
+    int64_t *tkey;  // [kJoinCap + 1] key of build row i
+    int64_t *tp;    // [kJoinCap] payload of build row i
+    uint16_t *tn;   // [kJoinCap + 1] next row in i's chain
+    uint32_t *head; // [kJoinHeads] last row inserted per bucket
+    int64_t *cw;    // [kCells]
+    int64_t *s_excl, *s_total;
+};
+
+// Sub-bucket s of one merge: build rows [bL, bL + nb), probe rows [bR, eR).
+// Publishes its output count to the merge's chained scan (jstatus) and its
+// first output row to jbase[s], then writes its output rows.  With CHUNKED,
+// a build side larger than the table is joined one table-sized chunk at a
+// time (every chunk against every probe row: each pair of rows meets once);
+// otherwise nb <= kJoinCap.
+template <typename K, bool CHUNKED>
+__device__ __forceinline__ void join_sub_bucket(const K *__restrict__ lk,
+                                                const int64_t *__restrict__ lv, int64_t bL,
+                                                int64_t nb, const K *__restrict__ rk,
+                                                const int64_t *__restrict__ rv, int64_t bR,
+                                                int64_t eR, uint64_t *jstatus, int64_t *jbase,
+                                                int64_t s, const ProbeOut &o, int32_t *status,
+                                                const JoinLds &L)
+{
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    K *out_key = (K *)o.key;
+    const int64_t nbatch = (eR - bR + kJoinBatch - 1) / kJoinBatch;
+    K kk[kJoinRows];
+    int64_t vv[kJoinRows];
+    uint32_t mf[kJoinRows];
+
+    if (CHUNKED && nb > kJoinCap && nbatch > 0) {
+        const int64_t nch = (nb + kJoinCap - 1) / kJoinCap;
+        int64_t total = 0;
+        for (int64_t c = 0; c < nch; ++c) {
+            const int64_t c0 = c * kJoinCap;
+            build_table(lk, lv, bL + c0, nb - c0 < kJoinCap ? nb - c0 : (int64_t)kJoinCap, L.tkey,
+                        L.tp, L.tn, L.head);
+            for (int64_t b = 0; b < nbatch; ++b) {
+                load_batch(rk, rv, bR + b * kJoinBatch, eR, kk, vv);
+                match_batch(bR + b * kJoinBatch, eR, true, L.tkey, L.tn, L.head, kk, mf);
+                cell_sums(mf, L.cw, lane, wv);
+                __syncthreads();
+                if (wv == 0) {
+                    const int64_t all = cell_total(L.cw, lane);
+                    if (lane == 0)
+                        *L.s_total = all;
+                }
+                __syncthreads();
+                total += *L.s_total;
+            }
+        }
+        if (wv == 0) {
+            const int64_t ex = lookback(jstatus, s, total, lane, status);
+            if (lane == 0) {
+                *L.s_excl = ex;
+                jbase[s] = ex;
+            }
+        }
+        __syncthreads();
+        const int64_t E = *L.s_excl;
+        if (E + total > o.cap) {
+            if (tid == 0 && total > 0)
+                or_status(status, MDX_DEV_OUTPUT_OVERFLOW);
+            return;
+        }
+        int64_t run = E;
+        for (int64_t c = 0; c < nch && total > 0; ++c) {
+            const int64_t c0 = c * kJoinCap;
+            build_table(lk, lv, bL + c0, nb - c0 < kJoinCap ? nb - c0 : (int64_t)kJoinCap, L.tkey,
+                        L.tp, L.tn, L.head);
+            for (int64_t b = 0; b < nbatch; ++b) {
+                load_batch(rk, rv, bR + b * kJoinBatch, eR, kk, vv);
+                match_batch(bR + b * kJoinBatch, eR, true, L.tkey, L.tn, L.head, kk, mf);
+                cell_sums(mf, L.cw, lane, wv);
+                __syncthreads();
+                if (wv == 0) {
+                    const int64_t all = cell_scan(L.cw, lane);
+                    if (lane == 0)
+                        *L.s_total = all;
+                }
+                __syncthreads();
+                emit_batch(kk, vv, mf, L.cw, run, L.tkey, L.tp, L.tn, out_key, o.lpay, o.rpay, lane,
+                           wv);
+                run += *L.s_total;
+                __syncthreads();  // cw, s_total and the table are reused
+            }
+        }
+        return;
+    }
+
+    const bool any = nb > 0 && nbatch > 0;
+    // Build, with the first probe batch's loads issued before the inserts.
+    if (nbatch > 0)
+        load_batch(rk, rv, bR, eR, kk, vv);
+    if (any)
+        build_table(lk, lv, bL, nb, L.tkey, L.tp, L.tn, L.head);
+
+    // Count every probe row's matches.
+    int64_t total = 0;
+    for (int64_t b = 0; b < nbatch; ++b) {
+        if (b > 0)
+            load_batch(rk, rv, bR + b * kJoinBatch, eR, kk, vv);
+        match_batch(bR + b * kJoinBatch, eR, any, L.tkey, L.tn, L.head, kk, mf);
+        cell_sums(mf, L.cw, lane, wv);
+        __syncthreads();
+        if (wv == 0) {
+            const int64_t all = cell_total(L.cw, lane);
+            if (lane == 0)
+                *L.s_total = all;
+        }
+        __syncthreads();
+        total += *L.s_total;
+    }
+
+    // Chained scan over sub-buckets.
+    if (wv == 0) {
+        const int64_t ex = lookback(jstatus, s, total, lane, status);
+        if (lane == 0) {
+            *L.s_excl = ex;
+            jbase[s] = ex;
+        }
+    }
+    __syncthreads();
+    const int64_t E = *L.s_excl;
+
+    // Write the output rows.
+    if (E + total > o.cap) {
+        if (tid == 0 && total > 0)
+            or_status(status, MDX_DEV_OUTPUT_OVERFLOW);
+    } else if (total > 0) {
+        if (nbatch == 1) {
+            if (wv == 0)
+                cell_scan(L.cw, lane);
+            __syncthreads();
+            emit_batch(kk, vv, mf, L.cw, E, L.tkey, L.tp, L.tn, out_key, o.lpay, o.rpay, lane, wv);
+        } else {
+            int64_t run = E;
+            for (int64_t b = 0; b < nbatch; ++b) {
+                load_batch(rk, rv, bR + b * kJoinBatch, eR, kk, vv);
+                match_batch(bR + b * kJoinBatch, eR, any, L.tkey, L.tn, L.head, kk, mf);
+                cell_sums(mf, L.cw, lane, wv);
+                __syncthreads();
+                if (wv == 0) {
+                    const int64_t all = cell_scan(L.cw, lane);
+                    if (lane == 0)
+                        *L.s_total = all;
+                }
+                __syncthreads();
+                emit_batch(kk, vv, mf, L.cw, run, L.tkey, L.tp, L.tn, out_key, o.lpay, o.rpay, lane,
+                           wv);
+                run += *L.s_total;
+                __syncthreads();  // cw and s_total are reused by the next batch
+            }
+        }
+    }
+}
+
 // The kernel's kJoinPerCu workgroups of kJoinThreads fill a CU's 4 SIMDs
 // with kJoinSimdWaves waves each.
 constexpr int kJoinSimdWaves = kJoinPerCu * kJoinThreads / (4 * kWave);
+
+// Sub-buckets are taken strictly in ticket order, just before each is
+// started: a ticket taken ahead of time would make later sub-buckets wait
+// for it in the chained scan.
+#define MDX_JOIN_LDS                                                                       \
+    __shared__ int64_t tkey[kJoinCap + 1];                                                 \
+    __shared__ int64_t tp[kJoinCap];                                                       \
+    __shared__ uint16_t tn[kJoinCap + 1];                                                  \
+    __shared__ uint32_t head[kJoinHeads];                                                  \
+    __shared__ int64_t cw[kCells];                                                         \
+    __shared__ int64_t s_next, s_excl, s_total;                                            \
+    const JoinLds L = {tkey, tp, tn, head, cw, &s_excl, &s_total};                         \
+    if (threadIdx.x == 0) {                                                                \
+        tkey[kSent] = 0;                                                                   \
+        tn[kSent] = (uint16_t)kSent;                                                       \
+    }
+
+// Next ticket, the same on every lane.
+__device__ __forceinline__ int64_t take_ticket(uint32_t *ticket, int64_t *s_next)
+{
+    if (threadIdx.x == 0)
+        *s_next = (int64_t)atomicAdd(ticket, 1u);
+    __syncthreads();
+    const int64_t t = uniform(*s_next);
+    __syncthreads();  // everyone has read s_next before it is replaced
+    return t;
+}
+
 template <typename K>
 __global__ __launch_bounds__(kJoinThreads)
 __attribute__((amdgpu_waves_per_eu(kJoinSimdWaves, kJoinSimdWaves))) void rj_join(
@@ -283,138 +510,71 @@ __attribute__((amdgpu_waves_per_eu(kJoinSimdWaves, kJoinSimdWaves))) void rj_joi
     const K *__restrict__ rk, const int64_t *__restrict__ rv, const int64_t *__restrict__ subR,
     RJoinWs w, ProbeOut o, int32_t *status)
 {
-    __shared__ int64_t tkey[kJoinCap + 1]; // key of build row i
-    __shared__ int64_t tp[kJoinCap];       // payload of build row i
-    __shared__ uint16_t tn[kJoinCap + 1];  // next row in i's chain
-    __shared__ uint32_t head[kJoinHeads];  // last row inserted per bucket
-    __shared__ int64_t cw[kCells];
-    __shared__ int64_t s_next, s_excl, s_total;
-
     if (*w.use == 0)
         return;
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-    K *out_key = (K *)o.key;
+    MDX_JOIN_LDS
     const int64_t S = w.S;
-    if (tid == 0) {
-        tkey[kSent] = 0;
-        tn[kSent] = (uint16_t)kSent;
-    }
-
-    // Sub-buckets are taken strictly in ticket order, just before each is
-    // started: a ticket taken ahead of time would make later sub-buckets wait
-    // for it in the chained scan.
     for (;;) {
-        if (tid == 0)
-            s_next = (int64_t)atomicAdd(w.ticket, 1u);
-        __syncthreads();
-        const int64_t s = uniform(s_next);
-        __syncthreads();  // everyone has read s_next before it is replaced
+        const int64_t s = take_ticket(w.ticket, &s_next);
         if (s >= S)
             break;
         const int64_t bL = subL[s], nb = subL[s + 1] - bL;  // nb <= kJoinCap (plan flag)
-        const int64_t bR = subR[s], eR = subR[s + 1];
-        const int64_t nbatch = (eR - bR + kJoinBatch - 1) / kJoinBatch;
-        const bool any = nb > 0 && nbatch > 0;
-
-        // Build: insert the sub-bucket's rows into the LDS table, kBuildBatch
-        // rows per thread at a time; the first probe batch's loads are issued
-        // before the inserts.
-        K kk[kJoinRows];
-        int64_t vv[kJoinRows];
-        uint32_t mf[kJoinRows];
-        if (nbatch > 0)
-            load_batch(rk, rv, bR, eR, kk, vv);
-        if (any) {
-            for (int i = tid; i < kJoinHeads; i += kJoinThreads)
-                head[i] = kSent;
-            __syncthreads();
-            // rows past nb load the last build row (no branch per load)
-            const K *kb = lk + bL;
-            const int64_t *vb = lv + bL;
-            const uint32_t last = (uint32_t)nb - 1;
-            for (int base = 0; base < (int)nb; base += kBuildBatch * kJoinThreads) {
-                K bk[kBuildBatch];
-                int64_t bv[kBuildBatch];
-#pragma unroll
-                for (int j = 0; j < kBuildBatch; ++j) {
-                    uint32_t i = (uint32_t)(base + j * kJoinThreads) + tid;
-                    i = i < last ? i : last;
-                    bk[j] = __builtin_nontemporal_load(kb + i);
-                    bv[j] = __builtin_nontemporal_load(vb + i);
-                }
-#pragma unroll
-                for (int j = 0; j < kBuildBatch; ++j) {
-                    const int i = base + j * kJoinThreads + tid;
-                    if (i < nb) {
-                        const int64_t k = (int64_t)bk[j];
-                        tkey[i] = k;
-                        tp[i] = bv[j];
-                        tn[i] = (uint16_t)atomicExch(&head[bucket_of(k)], (uint32_t)i);
-                    }
-                }
-            }
-            __syncthreads();
-        }
-
-        // Count every probe row's matches.
-        int64_t total = 0;
-        for (int64_t b = 0; b < nbatch; ++b) {
-            if (b > 0)
-                load_batch(rk, rv, bR + b * kJoinBatch, eR, kk, vv);
-            match_batch(bR + b * kJoinBatch, eR, any, tkey, tn, head, kk, mf);
-            cell_sums(mf, cw, lane, wv);
-            __syncthreads();
-            if (wv == 0) {
-                const int64_t all = cell_total(cw, lane);
-                if (lane == 0)
-                    s_total = all;
-            }
-            __syncthreads();
-            total += s_total;
-        }
-
-        // Chained scan over sub-buckets.
-        if (wv == 0) {
-            const int64_t ex = lookback(w.status, s, total, lane, status);
-            if (lane == 0) {
-                s_excl = ex;
-                w.tile_base[s] = ex;
-            }
-        }
-        __syncthreads();
-        const int64_t E = s_excl;
-
-        // Write the output rows.
-        if (E + total > o.cap) {
-            if (tid == 0 && total > 0)
-                or_status(status, MDX_DEV_OUTPUT_OVERFLOW);
-        } else if (total > 0) {
-            if (nbatch == 1) {
-                if (wv == 0)
-                    cell_scan(cw, lane);
-                __syncthreads();
-                emit_batch(kk, vv, mf, cw, E, tkey, tp, tn, out_key, o.lpay, o.rpay, lane, wv);
-            } else {
-                int64_t run = E;
-                for (int64_t b = 0; b < nbatch; ++b) {
-                    load_batch(rk, rv, bR + b * kJoinBatch, eR, kk, vv);
-                    match_batch(bR + b * kJoinBatch, eR, any, tkey, tn, head, kk, mf);
-                    cell_sums(mf, cw, lane, wv);
-                    __syncthreads();
-                    if (wv == 0) {
-                        const int64_t all = cell_scan(cw, lane);
-                        if (lane == 0)
-                            s_total = all;
-                    }
-                    __syncthreads();
-                    emit_batch(kk, vv, mf, cw, run, tkey, tp, tn, out_key, o.lpay, o.rpay, lane, wv);
-                    run += s_total;
-                    __syncthreads();  // cw and s_total are reused by the next batch
-                }
-            }
-        }
+        join_sub_bucket<K, false>(lk, lv, bL, nb, rk, rv, subR[s], subR[s + 1], w.status,
+                                  w.tile_base, s, o, status, L);
         __syncthreads();  // the table is reused by the next sub-bucket
     }
+}
+
+// Every merge of a batch: tickets run over all merges' sub-buckets (merge m
+// owns tickets [Spre[m], Spre[m+1])), so the workgroups stay busy across
+// merges; each merge has its own chained scan.
+template <typename K>
+__global__ __launch_bounds__(kJoinThreads)
+__attribute__((amdgpu_waves_per_eu(kJoinSimdWaves, kJoinSimdWaves))) void rj_join_batch(
+    const JoinRec *__restrict__ B, const uint32_t *__restrict__ Spre, int M, uint32_t *ticket)
+{
+    MDX_JOIN_LDS
+    const int64_t total = Spre[M];
+    int64_t c0 = 0, c1 = 0;  // tickets of the merge whose record is loaded
+    JoinRec r = {};
+    for (;;) {
+        const int64_t t = take_ticket(ticket, &s_next);
+        if (t >= total)
+            break;
+        if (t < c0 || t >= c1) {
+            const int m = find_range(Spre, M, (uint32_t)t);
+            c0 = Spre[m];
+            c1 = Spre[m + 1];
+            r = B[m];
+        }
+        const int64_t s = t - c0;
+        const int64_t *subL = r.subL, *subR = r.subR;
+        const int64_t bL = subL[s];
+        join_sub_bucket<K, true>((const K *)r.lk, r.lv, bL, subL[s + 1] - bL, (const K *)r.rk,
+                                 r.rv, subR[s], subR[s + 1], r.jstatus, r.jbase, s, r.o, r.status,
+                                 L);
+        __syncthreads();  // the table is reused by the next sub-bucket
+    }
+}
+
+// Block m: clear merge m's chained scan.  Block 0 also resets the ticket.
+__global__ __launch_bounds__(kBlock) void rj_clear_batch(const JoinRec *__restrict__ B,
+                                                         uint32_t *ticket)
+{
+    const JoinRec &r = B[blockIdx.x];
+    for (int64_t s = threadIdx.x; s < r.S; s += kBlock)
+        r.jstatus[s] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        *ticket = 0;
+}
+
+// Block m: merge m's output offsets from its chained scan.
+__global__ __launch_bounds__(kBlock) void rj_finalize_batch(const JoinRec *__restrict__ B)
+{
+    const JoinRec &r = B[blockIdx.x];
+    const int64_t total = (int64_t)(ld_agent(r.jstatus + r.S - 1) & kValMask);
+    for (int p = threadIdx.x; p <= r.P; p += kBlock)
+        r.o.offsets[p] = p < r.P ? r.jbase[(int64_t)p << r.qbits] : total;
 }
 
 // Output offsets of a merge: from the radix join's chained scan when it ran
@@ -476,6 +636,26 @@ hipError_t launch_rjoin(const void *lk, const int64_t *lv, const int64_t *subL, 
                            (const int32_t *)lk, lv, subL, (const int32_t *)rk, rv, subR, w, o,
                            status);
     trace_end("rj_join", s);
+    return hipGetLastError();
+}
+
+hipError_t launch_rjoin_batch(const JoinRec *recs, int M, const uint32_t *Spre, uint32_t S,
+                              uint32_t *ticket, int key_bytes, hipStream_t s)
+{
+    if (M <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(rj_clear_batch, dim3((unsigned)M), dim3(kBlock), 0, s, recs, ticket);
+    const int64_t cus = device_fill_blocks() / 8 > 0 ? device_fill_blocks() / 8 : 1;
+    const int G = (int)std::max<int64_t>(1, std::min<int64_t>(cus * kJoinPerCu, S));
+    trace_begin("rj_join", s);
+    if (key_bytes == 8)
+        hipLaunchKernelGGL(rj_join_batch<int64_t>, dim3(G), dim3(kJoinThreads), 0, s, recs, Spre,
+                           M, ticket);
+    else
+        hipLaunchKernelGGL(rj_join_batch<int32_t>, dim3(G), dim3(kJoinThreads), 0, s, recs, Spre,
+                           M, ticket);
+    trace_end("rj_join", s);
+    hipLaunchKernelGGL(rj_finalize_batch, dim3((unsigned)M), dim3(kBlock), 0, s, recs);
     return hipGetLastError();
 }
 

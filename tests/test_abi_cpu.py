@@ -216,6 +216,94 @@ def test_batch_validation():
     assert L._batch(2, None, 2, ws, need, None) == mdx.MDX_ERR_INVALID
 
 
+def _fused_bytes(descs, tunings=None):
+    arr = (L.mdx_merge_desc * max(len(descs), 1))(*descs)
+    tarr = None
+    if tunings is not None:
+        tarr = (L.mdx_batch_tuning * len(tunings))()
+        for i, (f, o, r, z) in enumerate(tunings):
+            tarr[i].fill, tarr[i].fanout, tarr[i].part_rows, tarr[i].reserved = f, o, r, z
+    lo, hi = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    st = L._fb_ws(len(descs), arr, tarr, ctypes.byref(lo), ctypes.byref(hi))
+    return st, lo.value, hi.value
+
+
+def test_fused_batch_workspace():
+    a, b, c = _desc(100_000, 100_000, 8), _desc(60_000, 9_000, 4, 4), _desc(0, 5_000, 32)
+    st, lo0, hi0 = _fused_bytes([])
+    assert st == mdx.MDX_OK and lo0 == hi0
+    st, lo1, hi1 = _fused_bytes([a])
+    assert st == mdx.MDX_OK and lo1 == hi1 and lo1 > lo0
+    st, lo, hi = _fused_bytes([a, b, c])
+    assert st == mdx.MDX_OK and lo % 256 == 0 and hi % 256 == 0
+    assert lo < hi  # the least workspace holds the largest merge, one wave holds all
+    # per-merge workspace grows with either side
+    prev = 0
+    for n in [0, 1, 1000, 10**4, 10**5, 10**6]:
+        st, lo_n, _ = _fused_bytes([_desc(n, 1000)])
+        assert st == mdx.MDX_OK and lo_n >= prev
+        prev = lo_n
+    # tuning: fuller sub-buckets never need more workspace
+    st, lo_f, _ = _fused_bytes([a], [(0.9, 0, 0, 0)])
+    st2, lo_e, _ = _fused_bytes([a], [(0.3, 0, 0, 0)])
+    assert st == st2 == mdx.MDX_OK and lo_f <= lo_e
+
+
+@pytest.mark.parametrize("tuning", [(0.01, 0, 0, 0), (1.5, 0, 0, 0), (float("nan"), 0, 0, 0),
+                                    (0.8, -1, 0, 0), (0.8, mdx.MDX_MAX_P + 1, 0, 0),
+                                    (0.8, 128, 4, 0), (0.8, 128, 8, 1)])
+def test_fused_batch_rejects_bad_tuning(tuning):
+    st, _, _ = _fused_bytes([_desc(1000, 1000), _desc(10, 10)], [(0, 0, 0, 0), tuning])
+    assert st == mdx.MDX_ERR_INVALID
+    assert "merge 1" in mdx.last_error()
+
+
+def test_fused_batch_create_validation():
+    """Every check mdx_batch_create makes before its pinned allocation."""
+    good = [_desc(1000, 1000, base=FAKE + (i << 33)) for i in range(3)]
+    st, lo, hi = _fused_bytes(good)
+    assert st == mdx.MDX_OK
+    ws = FAKE + (64 << 30)
+    h = ctypes.c_void_p()
+
+    def create(descs, w=ws, wb=hi, tun=None):
+        arr = (L.mdx_merge_desc * max(len(descs), 1))(*descs)
+        return L._fb_create(len(descs), arr, tun, w, wb, ctypes.byref(h))
+
+    assert create(good, wb=lo - 256) == mdx.MDX_ERR_WORKSPACE
+    assert create(good, w=ws + 64) == mdx.MDX_ERR_INVALID
+    assert create(good, w=None) == mdx.MDX_ERR_INVALID
+    bad = list(good); bad[1] = _desc(1000, 1000, P=0, base=FAKE + (1 << 33))
+    assert create(bad) == mdx.MDX_ERR_INVALID and "merge 1" in mdx.last_error()
+    bad = list(good); bad[2] = _desc(1000, 1000, cap=-1, base=FAKE + (2 << 33))
+    assert create(bad) == mdx.MDX_ERR_INVALID and "merge 2" in mdx.last_error()
+    bad = list(good); bad[0] = _desc(1000, 1000, base=FAKE); bad[0].d_out_key = ws + 4096
+    assert create(bad) == mdx.MDX_ERR_INVALID  # an output inside the workspace
+    assert L._fb_create(-1, None, None, ws, hi, ctypes.byref(h)) == mdx.MDX_ERR_INVALID
+    assert L._fb_create(2, None, None, ws, hi, ctypes.byref(h)) == mdx.MDX_ERR_INVALID
+    arr = (L.mdx_merge_desc * 3)(*good)
+    assert L._fb_create(3, arr, None, ws, hi, None) == mdx.MDX_ERR_INVALID
+    assert L._fb_run(None, None) == mdx.MDX_ERR_INVALID
+    assert L._fb_destroy(None) == mdx.MDX_OK
+    w, n = ctypes.c_int32(), ctypes.c_int32()
+    assert L._fb_info(None, ctypes.byref(w), ctypes.byref(n)) == mdx.MDX_ERR_INVALID
+
+
+def test_autotune_lookup_reads_cells(tmp_path):
+    import json
+    from paper_2101_08878_amd import autotune
+    path = str(tmp_path / "t.json")
+    cells = [{"key_bytes": 8, "lo": 1000, "hi": 4000, "tuning": {"fill": 0.5, "fanout": 32,
+                                                                 "part_rows": 2}}]
+    with open(path, "w") as f:
+        json.dump({"cells": cells}, f)
+    assert autotune.lookup(8, 1000, path) == {"fill": 0.5, "fanout": 32, "part_rows": 2}
+    assert autotune.lookup(8, 3999, path)["fanout"] == 32
+    assert autotune.lookup(8, 4000, path) == {}
+    assert autotune.lookup(4, 2000, path) == {}
+    assert autotune.lookup(8, 2000, str(tmp_path / "missing.json")) == {}
+
+
 def test_merge_workspace_monotone_in_both_sides():
     """A server slot and a batch lane are sized at the largest merge they
     take, which covers every smaller one only if a merge's workspace never

@@ -119,3 +119,111 @@ def test_batch_config4_subset():
     mdx.mdx_merge_batch(jobs, lanes=4)
     torch.cuda.synchronize()
     _check(items, jobs)
+
+
+# ---- fused batches (mdx_batch_*) ---------------------------------------------------------
+
+FUSED_TUNINGS = [None, {"fill": 0.5, "fanout": 32, "part_rows": 2},
+                 {"fill": 1.0, "fanout": 256, "part_rows": 8}]
+
+
+@pytest.mark.parametrize("tuning", FUSED_TUNINGS, ids=["default", "small", "full-tables"])
+def test_fused_batch_matches_oracle(tuning):
+    """Every merge of the mixed batch; fill 1.0 leaves many build sub-buckets
+    larger than a table, so they take the chunked join, as the merge with
+    20000 copies of one key does under every tuning."""
+    import paper_2101_08878_amd as mdx
+    announce(f"fused batch tuning={tuning}")
+    items = _batch_inputs()
+    jobs = _jobs(items)
+    fb = mdx.FusedBatch(jobs, tuning=tuning)
+    waves, launches = fb.info()
+    assert waves == 1 and 0 < launches < 40
+    fb.run()
+    torch.cuda.synchronize()
+    _check(items, jobs)
+    fb.close()
+
+
+def test_fused_batch_in_many_waves():
+    """The least workspace: every wave holds as many merges as fit; the
+    result does not depend on the waves."""
+    import paper_2101_08878_amd as mdx
+    announce("fused batch, least workspace")
+    items = _batch_inputs()
+    jobs = _jobs(items)
+    lo, hi = mdx.mdx_batch_workspace_bytes(jobs)
+    fb = mdx.FusedBatch(jobs, workspace_bytes=lo)
+    waves, _ = fb.info()
+    assert waves > 1
+    fb.run()
+    torch.cuda.synchronize()
+    _check(items, jobs)
+    fb.close()
+
+
+def test_fused_batch_overflow_and_chunks():
+    """A repeated key whose output exceeds the capacity: the chunked join
+    counts it exactly and reports the overflow; the merge beside it is
+    unaffected."""
+    import paper_2101_08878_amd as mdx
+    announce("fused batch: output overflow in the chunked join")
+    kl = np.concatenate([np.full(9000, 7, np.int64), np.arange(100, 20000, dtype=np.int64)])
+    kr = np.concatenate([np.full(40, 7, np.int64), np.arange(0, 30000, 3, dtype=np.int64)])
+    items = [(kl, np.arange(kl.size, dtype=np.int64), kr, np.arange(kr.size, dtype=np.int64), 4)]
+    items.append(_batch_inputs()[0])
+    jobs = _jobs(items)
+    total = jobs[0].out_capacity
+    jobs[0].out_capacity = total - 1
+    mdx.FusedBatch(jobs).run()
+    torch.cuda.synchronize()
+    assert int(jobs[0].status.item()) & mdx.MDX_DEV_OUTPUT_OVERFLOW
+    ref = oracle.join(*items[0][:4], P=4, materialize=False)
+    off = host(jobs[0].out_offsets)
+    assert off[-1] == ref["total"] == total
+    assert np.array_equal(np.diff(off), ref["per_part"])
+    _check(items[1:], jobs[1:])
+
+
+def test_fused_batch_graph_replays():
+    """The batch captured into a graph (the plan's copy to the device and
+    every launch); three replays with eager clearing in between, each checked
+    against the oracle."""
+    import paper_2101_08878_amd as mdx
+    announce("fused batch in a HIP graph")
+    items = _batch_inputs()
+    jobs = _jobs(items)
+    fb = mdx.FusedBatch(jobs)
+    s = torch.cuda.Stream()
+    fb.run(s)  # kernels' attributes are set before capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        fb.run(s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for j in jobs:
+            for t in j.out:
+                t.fill_(-1)
+            j.out_offsets.fill_(-1)
+            j.status.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        _check(items, jobs)
+    del g
+    fb.close()
+
+
+def test_fused_batch_config4_subset():
+    """The first 16 merges of the 4096-merge batch at their real sizes, with
+    the tuning table."""
+    import paper_2101_08878_amd as mdx
+    announce("fused batch: first 16 merges of the 4096-merge batch")
+    items = [(*batch_tables(s), 8) for s in batch_specs(4096)[:16]]
+    jobs = _jobs(items)
+    fb = mdx.FusedBatch(jobs, tuning="table")
+    fb.run()
+    torch.cuda.synchronize()
+    _check(items, jobs)
+    fb.close()
