@@ -272,7 +272,9 @@ int32_t mdx_merge(const void *d_left_keys, const int64_t *d_left_payload, int64_
  * Merge i of h_descs[0..count) computes exactly what mdx_merge computes
  * with the same arguments (same output rows, same offsets, same device
  * status bits); merges are independent and may differ in sizes, key type
- * and P.  The merges run on up to `lanes` concurrent lanes: HIP streams the
+ * and P.  As in fused batches (below), a build sub-bucket too large for an
+ * LDS table is joined in table-sized chunks rather than by the global-table
+ * join, so a merge of a batch makes no launches for that join.  The merges run on up to `lanes` concurrent lanes: HIP streams the
  * library creates at the default priority on first use on a device and
  * keeps until the process ends.  The lanes are forked from `stream` and
  * joined back to it with events, so the batch is ordered on `stream` like a
@@ -400,9 +402,11 @@ int32_t mdx_batch_destroy(mdx_batch *batch);
  * + 16) + 8 (P + 1) -- stay within budget_bytes; otherwise it returns
  * MDX_BUSY and enqueues nothing.  Merges in different slots run
  * concurrently and overlap on the device; each computes exactly what
- * mdx_merge computes with the same arguments.  mdx_server_poll returns the
- * tags of merges that have finished (their outputs are complete and
- * visible to any stream) and frees their slots and budget.  `ready`, if not
+ * mdx_merge computes with the same arguments (and, as a batch does, joins
+ * a build sub-bucket too large for an LDS table in table-sized chunks).
+ * mdx_server_poll returns the tags of merges that have finished (their
+ * outputs are complete and visible to any stream) and frees their slots
+ * and budget.  `ready`, if not
  * NULL, is an event the merge waits for before reading its inputs.
  *
  * A server is used from one host thread at a time.  The caller keeps d_ws

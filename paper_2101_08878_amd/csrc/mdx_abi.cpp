@@ -550,7 +550,9 @@ struct MergeLayout {
         rv2_off, subL_off, subR_off, rjoin_off, table_off, probe_off, bytes;
 };
 
-MergeLayout merge_layout(int64_t nL, int64_t nR, int32_t P, int32_t kt)
+// chunked: the merge joins oversized build sub-buckets in chunks and has no
+// global-table join (no table or probe workspace).
+MergeLayout merge_layout(int64_t nL, int64_t nR, int32_t P, int32_t kt, bool chunked = false)
 {
     MergeLayout M;
     M.plan = merge_plan(nL, nR, P);
@@ -591,8 +593,8 @@ MergeLayout merge_layout(int64_t nL, int64_t nR, int32_t P, int32_t kt)
     take(M.subL_off, two ? (size_t)(M.S + 1) * 8 : 0);
     take(M.subR_off, two ? (size_t)(M.S + 1) * 8 : 0);
     take(M.rjoin_off, M.jl.bytes);
-    take(M.table_off, M.tl.bytes);
-    take(M.probe_off, M.ql.bytes);
+    take(M.table_off, chunked ? 0 : M.tl.bytes);
+    take(M.probe_off, chunked ? 0 : M.ql.bytes);
     M.bytes = o;
     return M;
 }
@@ -644,12 +646,15 @@ static int32_t check_merge_ws(const mdx_merge_desc &d, const void *ws, size_t ws
     return MDX_OK;
 }
 
-// Enqueue one checked merge on `stream`, workspace at d_ws.
-static hipError_t enqueue_merge(const mdx_merge_desc &d, void *d_ws, hipStream_t stream)
+// Enqueue one checked merge on `stream`, workspace at d_ws (its layout
+// merge_layout(..., chunked)).  chunked: oversized build sub-buckets are
+// joined in LDS chunks, so the global-table join's launches are left out.
+static hipError_t enqueue_merge(const mdx_merge_desc &d, void *d_ws, hipStream_t stream,
+                                bool chunked = false)
 {
     const int32_t P = d.P, key_type = d.key_type;
     const int64_t n_left = d.n_left, n_right = d.n_right;
-    const MergeLayout M = merge_layout(n_left, n_right, P, key_type);
+    const MergeLayout M = merge_layout(n_left, n_right, P, key_type, chunked);
     char *b = (char *)d_ws;
     const MergePlan &pl = M.plan;
     const int nA = (int)M.nA;
@@ -695,16 +700,16 @@ static hipError_t enqueue_merge(const mdx_merge_desc &d, void *d_ws, hipStream_t
     // 3. radix join of every sub-bucket in LDS, if every build sub-bucket fits
     const RJoinWs jw = rjoin_ws(b + M.rjoin_off, M.jl);
     if (e == hipSuccess)
-        e = launch_rjoin_plan(subL, subR, M.S, jw, stream);
+        e = launch_rjoin_plan(subL, subR, M.S, jw, chunked, stream);
     if (e == hipSuccess)
         e = launch_rjoin(lk, lv, subL, rk, rv, subR, key_type, P, pl.qbits, jw, o, d_status,
-                         stream);
+                         chunked, stream);
 
     // 4. otherwise (a sub-bucket too large for LDS: heavy key repetition),
     // the global-table join over the first-pass output; its kernels do
     // nothing when the radix join ran.  No sub-bucket can exceed the table
     // when the whole build side fits it: then they are not launched.
-    if (n_left <= kJoinCap) {
+    if (chunked || n_left <= kJoinCap) {
         if (e == hipSuccess)
             e = launch_merge_finalize(P, pl.qbits, jw, nullptr, o, stream);
         return e;
@@ -786,7 +791,8 @@ BatchPlan batch_plan(int32_t count, const mdx_merge_desc *h, int32_t lanes)
                 l = k;
         B.lane[(size_t)i] = l;
         load[(size_t)l] += h[i].n_left + h[i].n_right;
-        const size_t b = merge_layout(h[i].n_left, h[i].n_right, h[i].P, h[i].key_type).bytes;
+        const size_t b =
+            merge_layout(h[i].n_left, h[i].n_right, h[i].P, h[i].key_type, true).bytes;
         need[(size_t)l] = need[(size_t)l] > b ? need[(size_t)l] : b;
     }
     B.used = L;
@@ -881,7 +887,7 @@ int32_t mdx_merge_batch(int32_t count, const mdx_merge_desc *h_descs, int32_t la
             return e;
         // its lane's slice holds its layout; its output stays clear of the
         // whole batch workspace
-        const size_t need = merge_layout(d.n_left, d.n_right, d.P, d.key_type).bytes;
+        const size_t need = merge_layout(d.n_left, d.n_right, d.P, d.key_type, true).bytes;
         if (int32_t e = check_merge_ws(d, (char *)d_ws + B.lane_off[(size_t)B.lane[(size_t)i]],
                                        need, need, Wi.c_str()))
             return e;
@@ -912,7 +918,7 @@ int32_t mdx_merge_batch(int32_t count, const mdx_merge_desc *h_descs, int32_t la
     }
     for (size_t k = 0; k < B.order.size() && e == hipSuccess; ++k) {
         const int32_t i = B.order[k], l = B.lane[(size_t)i];
-        e = enqueue_merge(h_descs[i], (char *)d_ws + B.lane_off[(size_t)l], ls[l]);
+        e = enqueue_merge(h_descs[i], (char *)d_ws + B.lane_off[(size_t)l], ls[l], true);
     }
     if (B.used > 1) {
         // join every lane that was forked, even after an error, so that
@@ -1379,19 +1385,6 @@ struct mdx_server {
 
 namespace {
 
-// Workspace of one slot: the largest merge layout over both key types and
-// every P up to max_P at the largest sizes.
-size_t server_slot_bytes(int64_t max_left, int64_t max_right, int32_t max_P)
-{
-    size_t b = 0;
-    for (int32_t P = 1; P <= max_P; ++P)
-        for (int32_t kt : {MDX_KEY_I32, MDX_KEY_I64}) {
-            const size_t x = merge_layout(max_left, max_right, P, kt).bytes;
-            b = x > b ? x : b;
-        }
-    return align_up(b);
-}
-
 // Bytes a merge holds while it runs: its inputs and outputs.
 size_t request_bytes(const mdx_merge_desc &d)
 {
@@ -1434,6 +1427,20 @@ ProbeJobLayout probe_job_layout(int64_t n, int32_t P, int32_t kt)
     o += align_up(L.ql.bytes);
     L.bytes = o;
     return L;
+}
+
+// Workspace of one slot: the largest merge layout (chunked: a served merge
+// needs no global-table join) or probe job over both key types and every P
+// up to max_P at the largest sizes.
+size_t server_slot_bytes(int64_t max_left, int64_t max_right, int32_t max_P)
+{
+    size_t b = 0;
+    for (int32_t P = 1; P <= max_P; ++P)
+        for (int32_t kt : {MDX_KEY_I32, MDX_KEY_I64}) {
+            b = std::max(b, merge_layout(max_left, max_right, P, kt, true).bytes);
+            b = std::max(b, probe_job_layout(max_right, P, kt).bytes);
+        }
+    return align_up(b);
 }
 
 int32_t check_server_limits(int32_t slots, int64_t max_left, int64_t max_right, int32_t max_P,
@@ -1538,14 +1545,15 @@ int32_t mdx_server_submit(mdx_server *srv, const mdx_merge_desc *h_desc, int64_t
         return MDX_BUSY;
     char *ws = srv->d_ws + (size_t)s * srv->slot_bytes;
     if (int32_t e = check_merge_ws(d, ws, srv->slot_bytes,
-                                   merge_layout(d.n_left, d.n_right, d.P, d.key_type).bytes, W))
+                                   merge_layout(d.n_left, d.n_right, d.P, d.key_type, true).bytes,
+                                   W))
         return e;
     if (int32_t e = check_merge_ws(d, srv->d_ws, (size_t)srv->slots * srv->slot_bytes, 0, W))
         return e;
     hipStream_t st = srv->streams[(size_t)s];
     hipError_t e = ready ? hipStreamWaitEvent(st, ready, 0) : hipSuccess;
     if (e == hipSuccess)
-        e = enqueue_merge(d, ws, st);
+        e = enqueue_merge(d, ws, st, true);
     if (e == hipSuccess)
         e = hipEventRecord(srv->done[(size_t)s], st);
     if (e != hipSuccess)

@@ -425,14 +425,17 @@ hipError_t launch_probe_group(const void *pkeys, const int64_t *ppay, int key_by
 hipError_t launch_probe_finalize(int32_t P, const ProbeWs &w, const ProbeOut &o,
                                  const int32_t *skip, hipStream_t s);
 
-// Radix join: plan (chunk plan over the probe sub-buckets, the LDS-fit flag
-// from the build sub-buckets, cleared chained scan), join, output offsets.
+// Radix join: plan (the LDS-fit flag from the build sub-buckets, cleared
+// chained scan), join, output offsets.  chunked: a build sub-bucket larger
+// than a table is joined in table-sized chunks (the flag stays set and no
+// global-table join is needed); otherwise such a sub-bucket clears the flag
+// and the join does nothing.
 hipError_t launch_rjoin_plan(const int64_t *subL, const int64_t *subR, int64_t S,
-                             const RJoinWs &w, hipStream_t s);
+                             const RJoinWs &w, bool chunked, hipStream_t s);
 hipError_t launch_rjoin(const void *lk, const int64_t *lv, const int64_t *subL, const void *rk,
                         const int64_t *rv, const int64_t *subR, int key_bytes, int32_t P,
                         int qbits, const RJoinWs &w, const ProbeOut &o, int32_t *status,
-                        hipStream_t s);
+                        bool chunked, hipStream_t s);
 // Radix join of every merge of a batch (one key width): record m describes
 // merge m (its S sub-buckets, its chained scan jstatus/jbase of S entries,
 // output); Spre [M + 1] prefix of the merges' S in device memory, S its

@@ -65,8 +65,10 @@ __device__ __forceinline__ int64_t uniform(int64_t x)
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+// chunked: oversized build sub-buckets are joined in chunks (the LDS-fit
+// flag stays 1).
 __global__ __launch_bounds__(kBlock) void rj_plan(const int64_t *__restrict__ subL, int64_t S,
-                                                  RJoinWs w)
+                                                  RJoinWs w, int chunked)
 {
     int over = 0;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
@@ -74,7 +76,7 @@ __global__ __launch_bounds__(kBlock) void rj_plan(const int64_t *__restrict__ su
         w.status[s] = 0;
         over |= (subL[s + 1] - subL[s]) > kJoinCap;
     }
-    if (over)
+    if (over && !chunked)
         *w.use = 0;  // rj_plan_init set it to 1 before this kernel
     if (blockIdx.x == 0 && threadIdx.x == 0)
         *w.ticket = 0;
@@ -90,7 +92,7 @@ __global__ void rj_plan_init(RJoinWs w)
 constexpr int kPlanOnePerThread = 8;
 
 __global__ __launch_bounds__(kBlock) void rj_plan_one(const int64_t *__restrict__ subL, int64_t S,
-                                                      RJoinWs w)
+                                                      RJoinWs w, int chunked)
 {
     // Every thread's loads are issued together: indices past S are clamped
     // to S - 1 (S >= 1) and their results ignored, so no load sits behind a
@@ -113,7 +115,7 @@ __global__ __launch_bounds__(kBlock) void rj_plan_one(const int64_t *__restrict_
     }
     over = __syncthreads_or(over);
     if (threadIdx.x == 0) {
-        *w.use = over ? 0 : 1;
+        *w.use = over && !chunked ? 0 : 1;
         *w.ticket = 0;
     }
 }
@@ -503,14 +505,16 @@ __device__ __forceinline__ int64_t take_ticket(uint32_t *ticket, int64_t *s_next
     return t;
 }
 
-template <typename K>
+// CHUNKED: oversized build sub-buckets are joined in chunks; otherwise the
+// kernel does nothing unless the plan found that every one fits a table.
+template <typename K, bool CHUNKED>
 __global__ __launch_bounds__(kJoinThreads)
 __attribute__((amdgpu_waves_per_eu(kJoinSimdWaves, kJoinSimdWaves))) void rj_join(
     const K *__restrict__ lk, const int64_t *__restrict__ lv, const int64_t *__restrict__ subL,
     const K *__restrict__ rk, const int64_t *__restrict__ rv, const int64_t *__restrict__ subR,
     RJoinWs w, ProbeOut o, int32_t *status)
 {
-    if (*w.use == 0)
+    if (!CHUNKED && *w.use == 0)
         return;
     MDX_JOIN_LDS
     const int64_t S = w.S;
@@ -518,9 +522,9 @@ __attribute__((amdgpu_waves_per_eu(kJoinSimdWaves, kJoinSimdWaves))) void rj_joi
         const int64_t s = take_ticket(w.ticket, &s_next);
         if (s >= S)
             break;
-        const int64_t bL = subL[s], nb = subL[s + 1] - bL;  // nb <= kJoinCap (plan flag)
-        join_sub_bucket<K, false>(lk, lv, bL, nb, rk, rv, subR[s], subR[s + 1], w.status,
-                                  w.tile_base, s, o, status, L);
+        const int64_t bL = subL[s], nb = subL[s + 1] - bL;
+        join_sub_bucket<K, CHUNKED>(lk, lv, bL, nb, rk, rv, subR[s], subR[s + 1], w.status,
+                                    w.tile_base, s, o, status, L);
         __syncthreads();  // the table is reused by the next sub-bucket
     }
 }
@@ -600,24 +604,39 @@ __global__ __launch_bounds__(kBlock) void merge_finalize(int P, int qbits, RJoin
 }  // namespace
 
 hipError_t launch_rjoin_plan(const int64_t *subL, const int64_t *subR, int64_t S,
-                             const RJoinWs &w, hipStream_t s)
+                             const RJoinWs &w, bool chunked, hipStream_t s)
 {
     (void)subR;
     if (S <= kPlanOneMax) {
-        hipLaunchKernelGGL(rj_plan_one, dim3(1), dim3(kBlock), 0, s, subL, S, w);
+        hipLaunchKernelGGL(rj_plan_one, dim3(1), dim3(kBlock), 0, s, subL, S, w, (int)chunked);
         return hipGetLastError();
     }
     const int64_t cus = device_fill_blocks() / 8 > 0 ? device_fill_blocks() / 8 : 1;
     const int G = (int)std::min<int64_t>(cus, (S + kBlock - 1) / kBlock + 1);
     hipLaunchKernelGGL(rj_plan_init, dim3(1), dim3(1), 0, s, w);
-    hipLaunchKernelGGL(rj_plan, dim3(G), dim3(kBlock), 0, s, subL, S, w);
+    hipLaunchKernelGGL(rj_plan, dim3(G), dim3(kBlock), 0, s, subL, S, w, (int)chunked);
     return hipGetLastError();
+}
+
+template <bool CHUNKED>
+void launch_rjoin_kernel(int G, const void *lk, const int64_t *lv, const int64_t *subL,
+                         const void *rk, const int64_t *rv, const int64_t *subR, int key_bytes,
+                         const RJoinWs &w, const ProbeOut &o, int32_t *status, hipStream_t s)
+{
+    if (key_bytes == 8)
+        hipLaunchKernelGGL((rj_join<int64_t, CHUNKED>), dim3(G), dim3(kJoinThreads), 0, s,
+                           (const int64_t *)lk, lv, subL, (const int64_t *)rk, rv, subR, w, o,
+                           status);
+    else
+        hipLaunchKernelGGL((rj_join<int32_t, CHUNKED>), dim3(G), dim3(kJoinThreads), 0, s,
+                           (const int32_t *)lk, lv, subL, (const int32_t *)rk, rv, subR, w, o,
+                           status);
 }
 
 hipError_t launch_rjoin(const void *lk, const int64_t *lv, const int64_t *subL, const void *rk,
                         const int64_t *rv, const int64_t *subR, int key_bytes, int32_t P,
                         int qbits, const RJoinWs &w, const ProbeOut &o, int32_t *status,
-                        hipStream_t s)
+                        bool chunked, hipStream_t s)
 {
     (void)P;
     (void)qbits;
@@ -627,14 +646,10 @@ hipError_t launch_rjoin(const void *lk, const int64_t *lv, const int64_t *subL, 
     const int64_t cus = device_fill_blocks() / 8 > 0 ? device_fill_blocks() / 8 : 1;
     const int G = (int)std::max<int64_t>(1, std::min<int64_t>(cus * kJoinPerCu, w.S));
     trace_begin("rj_join", s);
-    if (key_bytes == 8)
-        hipLaunchKernelGGL(rj_join<int64_t>, dim3(G), dim3(kJoinThreads), 0, s,
-                           (const int64_t *)lk, lv, subL, (const int64_t *)rk, rv, subR, w, o,
-                           status);
+    if (chunked)
+        launch_rjoin_kernel<true>(G, lk, lv, subL, rk, rv, subR, key_bytes, w, o, status, s);
     else
-        hipLaunchKernelGGL(rj_join<int32_t>, dim3(G), dim3(kJoinThreads), 0, s,
-                           (const int32_t *)lk, lv, subL, (const int32_t *)rk, rv, subR, w, o,
-                           status);
+        launch_rjoin_kernel<false>(G, lk, lv, subL, rk, rv, subR, key_bytes, w, o, status, s);
     trace_end("rj_join", s);
     return hipGetLastError();
 }

@@ -175,8 +175,10 @@ def _batch_bytes(descs, lanes):
 
 def test_batch_workspace_plan():
     a, b, c = _desc(100_000, 100_000, 8), _desc(60_000, 60_000, 4, 4), _desc(50_000, 50_000, 32)
-    ws = [mdx.mdx_merge_workspace_bytes(d.n_left, d.n_right, d.P, d.key_type) for d in (a, b, c)]
-    assert all(w % 256 == 0 for w in ws)
+    # a merge of a batch needs less than mdx_merge (no global-table join)
+    ws = [_batch_bytes([d], 1)[1] for d in (a, b, c)]
+    full = [mdx.mdx_merge_workspace_bytes(d.n_left, d.n_right, d.P, d.key_type) for d in (a, b, c)]
+    assert all(w % 256 == 0 and 0 < w < f for w, f in zip(ws, full))
     assert _batch_bytes([], 4) == (mdx.MDX_OK, 0)
     assert _batch_bytes([a, b, c], 1) == (mdx.MDX_OK, max(ws))
     # largest first, each to the lane with the fewest rows: a | b, c
@@ -325,9 +327,17 @@ def test_merge_workspace_monotone_in_both_sides():
 def test_server_workspace_and_validation():
     """Server sizing and every argument check that runs before a stream or
     event is created (no GPU needed)."""
-    per = max(mdx.mdx_merge_workspace_bytes(10**6, 2 * 10**6, P, kt)
-              for P in range(1, 9) for kt in (4, 8))
+    # a slot holds a served merge (no global-table join: less than mdx_merge
+    # needs) of the limits, or a probe job of max_right rows
+    per = mdx.mdx_server_workspace_bytes(1, 10**6, 2 * 10**6, 8)
+    full = max(mdx.mdx_merge_workspace_bytes(10**6, 2 * 10**6, P, kt)
+               for P in range(1, 9) for kt in (4, 8))
+    lane = max(_batch_bytes([_desc(10**6, 2 * 10**6, P, kt)], 1)[1]
+               for P in range(1, 9) for kt in (4, 8))
+    assert per % 256 == 0 and lane <= per < full
     assert mdx.mdx_server_workspace_bytes(3, 10**6, 2 * 10**6, 8) == 3 * per
+    probe_only = mdx.mdx_server_workspace_bytes(1, 0, 2 * 10**6, 8)
+    assert probe_only >= mdx.mdx_join_probe_workspace_bytes(2 * 10**6, 8, 8)
     out = ctypes.c_size_t(0)
     for args in [(0, 10, 10, 8), (mdx.MDX_MAX_SLOTS + 1, 10, 10, 8), (2, -1, 10, 8), (2, 10, 10, 0)]:
         assert L._srv_ws(*args, ctypes.byref(out)) == mdx.MDX_ERR_INVALID
