@@ -66,11 +66,13 @@ def parse():
     return ap.parse_args()
 
 
-def counted_traffic(kernel, workload, sources):
+def counted_traffic(kernel, workload):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (profiles/*traffic.json, written by paper_2101_08878_amd.rocprof_summary
     from FETCH_SIZE and WRITE_SIZE runs), or None when there is none for the
-    current kernel sources."""
+    kernel's current sources."""
+    from paper_2101_08878_amd.rocprof_summary import kernel_sources_hash
+    sources = kernel_sources_hash(kernel)
     for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*traffic.json"))):
         with open(f) as fh:
             t = json.load(fh)
@@ -858,7 +860,7 @@ def run_transpose(args):
     nbytes = 16 * n * n
     achieved = nbytes / (kms / 1e3) / 1e9
     sources = kernel_sources_hash()
-    traffic, traffic_src = counted_traffic("transpose_sum", "transpose", sources)
+    traffic, traffic_src = counted_traffic("transpose_sum", "transpose")
     log(f"transpose sum {n} x {n}: {ms:.3f} ms/step, kernel {kms:.3f} ms, {achieved:.0f} GB/s")
     line = {
         "metric": "matrix elements/s for y = x + x^T, 16384 x 16384 float64",
@@ -1000,7 +1002,7 @@ def main():
             avg_s = sum(d) / len(d) / 1e3
             launches = t.launches() / prof_steps
             cb = credited_bytes(name, nl, nr, key_bytes, total) / launches
-            counted, _ = counted_traffic(name, args.config, sources)
+            counted, _ = counted_traffic(name, args.config)
             kernels[name] = {
                 "ms_per_step": round(sum(d) / prof_steps, 4),
                 "launches_per_step": launches,

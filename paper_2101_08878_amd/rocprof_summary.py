@@ -34,12 +34,24 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
-def kernel_sources_hash() -> str:
-    """Hash of the HIP/C++ sources of libmdx: counter figures taken on other
-    sources no longer describe the kernels."""
-    h = hashlib.sha256()
+# The source file that defines each traced kernel.
+KERNEL_FILES = {
+    "part_hist": "partition.hip", "part_scatter": "partition.hip", "seg_hist": "partition.hip",
+    "seg_scatter": "partition.hip", "rj_join": "rjoin.hip", "transpose_sum": "transpose.hip",
+    "transpose_sum_tiles": "transpose.hip",
+}
+SHARED_FILES = ("mdx_device.hpp", "mdx_internal.hpp")
+
+
+def kernel_sources_hash(kernel: str | None = None) -> str:
+    """Hash of the sources a kernel is built from (its own file and the
+    shared device headers; every HIP/C++ source when the kernel is not
+    known): counter figures taken on other sources no longer describe it."""
     csrc = os.path.join(HERE, "csrc")
-    for f in sorted(os.listdir(csrc)):
+    own = KERNEL_FILES.get(kernel or "")
+    files = sorted((own,) + SHARED_FILES) if own else sorted(os.listdir(csrc))
+    h = hashlib.sha256()
+    for f in files:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
@@ -114,7 +126,7 @@ def traffic(args):
         "kernel": args.report_as or args.kernel,
         "device_kernel": args.kernel,
         "workload": args.workload,
-        "kernel_sources": kernel_sources_hash(),
+        "kernel_sources": kernel_sources_hash(args.report_as or args.kernel),
         "fetch_kib_per_launch": round(f_kib, 1),
         "write_kib_per_launch": round(w_kib, 1),
         "launches": [len(kf), len(kw)],
