@@ -82,6 +82,8 @@ def _trace_rows(d):
 
 def trace(args):
     rows = sorted(_trace_rows(args.dir), key=lambda r: -r[2])
+    if args.include:
+        rows = [r for r in rows if re.search(args.include, r[0])]
     out = [f"# {args.title}", "", "Command (run from the repository root on one MI355X):", "",
            "```", args.cmd, "```", ""]
     if args.note:
@@ -152,6 +154,7 @@ def main(argv=None):
     t.add_argument("--title", required=True)
     t.add_argument("--cmd", required=True)
     t.add_argument("--note", default="")
+    t.add_argument("--include", default="", help="only kernels whose name matches this regex")
     c = sub.add_parser("traffic")
     c.add_argument("fetch_dir")
     c.add_argument("write_dir")
