@@ -227,3 +227,46 @@ def test_fused_batch_config4_subset():
     torch.cuda.synchronize()
     _check(items, jobs)
     fb.close()
+
+
+def test_fused_batch_many_small_merges():
+    """8500 merges of 0 to 60 rows (about 4250 per key width, so each launch
+    covers more merges than two 64-way rounds of the block-range search
+    resolve: three rounds), empty sides, P from 1 to 9."""
+    import paper_2101_08878_amd as mdx
+    announce("fused batch: 8500 small merges")
+    rng = np.random.default_rng(5)
+    items = []
+    for i in range(8500):
+        nl, nr = int(rng.integers(0, 61)), int(rng.integers(0, 61))
+        kd = np.int32 if i % 2 else np.int64
+        kl = rng.integers(-20, 20, nl).astype(kd)
+        kr = rng.integers(-20, 20, nr).astype(kd)
+        items.append((kl, np.arange(nl, dtype=np.int64), kr, np.arange(nr, dtype=np.int64),
+                      int(rng.integers(1, 10))))
+    jobs = _jobs(items)
+    fb = mdx.FusedBatch(jobs)
+    fb.run()
+    torch.cuda.synchronize()
+    _check(items, jobs)
+    fb.close()
+
+
+@pytest.mark.parametrize("P", [300, 4096])
+def test_fused_batch_many_partitions(P):
+    """More than 256 destinations in the first pass: 1024-row tiles, with a
+    merge of the default shape beside it in the same wave."""
+    import paper_2101_08878_amd as mdx
+    announce(f"fused batch: P={P}")
+    items = []
+    for s in batch_specs(3, seed=3, lo=1e3, hi=3e5):
+        kl, vl, kr, vr = batch_tables(s, seed=3)
+        items.append((kl, vl, kr, vr, P))
+    kl, vl, kr, vr = batch_tables(batch_specs(1, seed=4, lo=1e4, hi=1e5)[0], seed=4)
+    items.append((kl, vl, kr, vr, 8))
+    jobs = _jobs(items)
+    fb = mdx.FusedBatch(jobs, tuning=[{}, {"part_rows": 8}, {"fanout": 4096}, {}])
+    fb.run()
+    torch.cuda.synchronize()
+    _check(items, jobs)
+    fb.close()
