@@ -681,11 +681,13 @@ def run_serving(args):
 def run_skewed(args):
     """The skewed workload: 5E7 x 5E7 rows, int64 keys Zipf(1.1) over 1E7
     values, P = 16.  Its join has ~5E13 rows, so the graded step is the part
-    that does not write them: both partitions, the build of the left table,
-    and the count-only probe of the right (the exact per-partition output
-    counts).  Then the output is materialized on the window L x R[0:m), m the
-    longest prefix of right rows whose output stays within 2^28 rows, and
-    its rows are checked."""
+    that does not write them: both partitions, then the count-only join
+    (mdx_join_count: a table of build-row counts per key, probed by the right
+    keys) giving the exact per-partition output counts.  The same counts
+    through the reusable table (mdx_join_build, then mdx_join_probe with no
+    output) are timed beside it.  Then the output is materialized on the
+    window L x R[0:m), m the longest prefix of right rows whose output stays
+    within 2^28 rows, and its rows are checked."""
     import numpy as np
     import torch
 
@@ -710,20 +712,32 @@ def run_skewed(args):
     wsr = torch.empty(mdx.mdx_hash_partition_workspace_bytes(nr, P), dtype=torch.uint8, device=dev)
     tmem = torch.empty(mdx.mdx_join_table_bytes(nl, P), dtype=torch.uint8, device=dev)
     pws = torch.empty(mdx.mdx_join_probe_workspace_bytes(nr, P), dtype=torch.uint8, device=dev)
+    cws = torch.empty(mdx.mdx_join_count_workspace_bytes(nl, nr, P), dtype=torch.uint8, device=dev)
     status = torch.zeros(1, dtype=torch.int32, device=dev)
+    tstatus = torch.zeros(1, dtype=torch.int32, device=dev)
+    toff = torch.empty(P + 1, dtype=torch.int64, device=dev)
     empty = (torch.empty(0, dtype=torch.int64, device=dev),) * 3
 
-    def step():
+    def partitions():
         mdx.mdx_hash_partition(lk, lv, P, keys_out=lko, payload_out=lvo, offsets=lo, workspace=wsl,
                                stream=stream)
         mdx.mdx_hash_partition(rk, rv, P, keys_out=rko, payload_out=rvo, offsets=ro, workspace=wsr,
                                stream=stream)
-        t = mdx.mdx_join_build(lko, lvo, lo, P, table_memory=tmem, status=status, stream=stream)
-        mdx.mdx_join_probe(t, rko, rvo, ro, out_capacity=0, out=empty, out_offsets=off,
-                           workspace=pws, status=status, stream=stream)
+
+    def step():
+        partitions()
+        mdx.mdx_join_count(lko, lo, rko, ro, P, out_offsets=off, workspace=cws, status=status,
+                           stream=stream)
+
+    def step_table():
+        partitions()
+        t = mdx.mdx_join_build(lko, lvo, lo, P, table_memory=tmem, status=tstatus, stream=stream)
+        mdx.mdx_join_probe(t, rko, rvo, ro, out_capacity=0, out=empty, out_offsets=toff,
+                           workspace=pws, status=tstatus, stream=stream)
 
     for _ in range(args.warmup):
         step()
+        step_table()
     torch.cuda.synchronize()
     # the closed form: |J| = sum over keys of countL(k) countR(k)
     cl = torch.bincount(lk, minlength=spec.zipf_support + 1)
@@ -731,34 +745,48 @@ def run_skewed(args):
     want = int((cl * cr).sum().item())
     total = int(off[-1].item())
     # a count-only probe (capacity 0) reports its rows as an overflow
-    st = int(status.item()) & ~mdx.MDX_DEV_OUTPUT_OVERFLOW
-    if st != 0 or total != want:
-        raise SystemExit(f"skewed: count {total} (expected {want}), device status {st}")
-    log(f"output rows (counted, not written): {total:.4g}")
+    tst = int(tstatus.item()) & ~mdx.MDX_DEV_OUTPUT_OVERFLOW
+    if int(status.item()) != 0 or total != want or tst != 0 or not torch.equal(off, toff):
+        raise SystemExit(f"skewed: count {total} (expected {want}), device status "
+                         f"{int(status.item())}, table path {int(toff[-1].item())} status {tst}")
+    log(f"output rows (counted, not written): {total:.4g}; both count paths equal the closed form")
+
+    def timed(fn, reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms = timed(step, args.steps)
+    log(f"partition + count-only join: {ms:.3f} ms/step, {(nl + nr) / (ms / 1e3):.4g} input rows/s")
+    tms = timed(step_table, args.steps)
+    log(f"partition + table build + count-only probe: {tms:.3f} ms/step")
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.steps):
-        step()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
-    log(f"partition + build + count: {ms:.3f} ms/step, {(nl + nr) / (ms / 1e3):.4g} input rows/s")
-    traces = {k: mdx.KernelTrace(k, 64) for k in mdx.TRACEABLE_KERNELS}
-    for t in traces.values():
-        t.start()
-    for _ in range(2):
-        step()
-    torch.cuda.synchronize()
-    mdx.KernelTrace.stop_all()
-    kernels = {}
-    for name, t in traces.items():
-        d = t.durations_ms()
-        if d:
-            kernels[name] = {"ms_per_step": round(sum(d) / 2, 4), "launches_per_step": t.launches() / 2,
-                             "avg_launch_us": round(sum(d) / len(d) * 1e3, 2)}
-        t.close()
-    for name, k in sorted(kernels.items(), key=lambda kv: -kv[1]["ms_per_step"]):
-        log(f"  {name:13s} {k['ms_per_step']:.3f} ms/step  {k['launches_per_step']:.0f} launches")
+    def breakdown(fn, label):
+        traces = {k: mdx.KernelTrace(k, 64) for k in mdx.TRACEABLE_KERNELS}
+        for t in traces.values():
+            t.start()
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        mdx.KernelTrace.stop_all()
+        ks = {}
+        for name, t in traces.items():
+            d = t.durations_ms()
+            if d:
+                ks[name] = {"ms_per_step": round(sum(d) / 2, 4), "launches_per_step": t.launches() / 2,
+                            "avg_launch_us": round(sum(d) / len(d) * 1e3, 2)}
+            t.close()
+        log(label)
+        for name, k in sorted(ks.items(), key=lambda kv: -kv[1]["ms_per_step"]):
+            log(f"  {name:13s} {k['ms_per_step']:.3f} ms/step  {k['launches_per_step']:.0f} launches")
+        return ks
+
+    kernels = breakdown(step, "graded step (partitions + count-only join):")
+    table_kernels = breakdown(step_table, "table path (partitions + build + count-only probe):")
 
     # the window: the longest prefix of right rows with at most 2^28 output rows
     c = torch.cumsum(cl[rk], 0)
@@ -795,19 +823,23 @@ def run_skewed(args):
     wms = e0.elapsed_time(e1) / reps
     wgbs = wrows * 24 / (wms / 1e3) / 1e9
     log(f"window merge: {wms:.3f} ms, {wgbs:.0f} GB/s of output written")
-    alg = (nl + nr) * 2 * 16 + nl * 32 + nr * 24  # partition, build, count-only probe
+    # partition (read + write 16 B per row); count: every key read (8 B) and
+    # its table slot written or read (16 B)
+    alg = (nl + nr) * 2 * 16 + (nl + nr) * 24
     achieved = alg / (ms / 1e3) / 1e9
     line = {
         "metric": "input rows/s for partition + build + count, 5E7 x 5E7 int64 Zipf(1.1) over 1E7 "
                   "values, P=16",
+        "table_path_ms": round(tms, 4),
         "value": round((nl + nr) / (ms / 1e3), 1), "unit": "input rows/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int64", "data": "synthetic",
         "config": {"workload": f"skewed: {nl} x {nr} rows, Zipf(1.1) keys over 1E7 values, P={P}; "
-                               "partitions, left build, right count-only probe",
+                               "partitions, then the count-only join (left keys counted per key, "
+                               "right keys probe the counts)",
                    "output_rows_counted": total},
-        "roofline": {"bound": "hbm", "scope": "partition of both tables + build + count-only probe",
+        "roofline": {"bound": "hbm", "scope": "partition of both tables + count-only join",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "algorithmic_bytes": int(alg)},
@@ -815,6 +847,7 @@ def run_skewed(args):
                    "output_write_gbs": round(wgbs, 1),
                    "input_rows_per_s": round((nl + m) / (wms / 1e3), 1)},
         "kernels": kernels,
+        "table_path_kernels": table_kernels,
         "kernel_sources": kernel_sources_hash(),
     }
     print(json.dumps(line), flush=True)

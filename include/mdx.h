@@ -233,6 +233,35 @@ int32_t mdx_join_probe(const mdx_table *h_table, const void *d_keys, const int64
                        hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * Join count: the per-partition output counts of the inner join of two
+ * partitioned tables, without materializing it.
+ *
+ * Section V-B ("cuDF Merge"): the size of every partition's merge output,
+ * sum over keys k of (build rows with key k) x (probe rows with key k) --
+ * what a worker needs to size its output, and all that can be computed when
+ * the output is too large to hold (heavily repeated keys).  The build keys
+ * are counted per distinct key into a hash table in the workspace (rows are
+ * first aggregated per workgroup, so a key repeated millions of times costs
+ * one global update per workgroup), then every probe key looks up its
+ * count.  Nothing is kept for later probes: the table lives in d_ws.
+ * Arguments: d_lkeys [n_build] and d_lofs [P+1] (a table partitioned by
+ * mdx_hash_partition), d_rkeys [n_probe] and d_rofs [P+1] likewise, both of
+ * key_type; d_ws of at least mdx_join_count_workspace_bytes(n_build,
+ * n_probe, P, key_type) bytes; d_out_offsets [P+1] int64 receives exactly
+ * what mdx_join_probe writes there (exclusive prefix of the per-partition
+ * counts, total in d_out_offsets[P]).  A row whose destination differs from
+ * the partition its offsets place it in is skipped and reported with
+ * MDX_DEV_BAD_PARTITIONING.
+ * ------------------------------------------------------------------------- */
+int32_t mdx_join_count_workspace_bytes(int64_t n_build, int64_t n_probe, int32_t P,
+                                       int32_t key_type, size_t *h_bytes);
+
+int32_t mdx_join_count(const void *d_lkeys, const int64_t *d_lofs, int64_t n_build,
+                       const void *d_rkeys, const int64_t *d_rofs, int64_t n_probe, int32_t P,
+                       int32_t key_type, void *d_ws, size_t ws_bytes, int64_t *d_out_offsets,
+                       int32_t *d_status, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Merge: the whole per-worker path in one call.
  *
  * Section V-B ("cuDF Merge") with Section IV-B's buffers: the hash shuffle's

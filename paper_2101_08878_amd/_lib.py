@@ -96,6 +96,9 @@ _build = _sig("mdx_join_build", _i32, _vp, _vp, _vp, _i64, _i32, _i32, _vp, _sz,
 _probe_ws = _sig("mdx_join_probe_workspace_bytes", _i32, _i64, _i32, _i32, ctypes.POINTER(_sz))
 _probe = _sig("mdx_join_probe", _i32, ctypes.POINTER(mdx_table), _vp, _vp, _vp, _i64, _vp, _sz,
               _vp, _vp, _vp, _i64, _vp, _vp, _vp)
+_count_ws = _sig("mdx_join_count_workspace_bytes", _i32, _i64, _i64, _i32, _i32, ctypes.POINTER(_sz))
+_count = _sig("mdx_join_count", _i32, _vp, _vp, _i64, _vp, _vp, _i64, _i32, _i32, _vp, _sz, _vp, _vp,
+              _vp)
 _merge_ws = _sig("mdx_merge_workspace_bytes", _i32, _i64, _i64, _i32, _i32, ctypes.POINTER(_sz))
 _merge = _sig("mdx_merge", _i32, _vp, _vp, _i64, _vp, _vp, _i64, _i32, _i32, _vp, _sz,
               _vp, _vp, _vp, _i64, _vp, _vp, _vp)
@@ -132,6 +135,7 @@ ABI_FUNCTIONS = [
     "mdx_hash_partition_workspace_bytes", "mdx_hash_partition", "mdx_hash_partition_noalloc",
     "mdx_join_table_bytes", "mdx_join_build",
     "mdx_join_probe_workspace_bytes", "mdx_join_probe",
+    "mdx_join_count_workspace_bytes", "mdx_join_count",
     "mdx_merge_workspace_bytes", "mdx_merge",
     "mdx_merge_batch_workspace_bytes", "mdx_merge_batch",
     "mdx_batch_workspace_bytes", "mdx_batch_create", "mdx_batch_info", "mdx_batch_run",
@@ -142,7 +146,8 @@ ABI_FUNCTIONS = [
     "mdx_transpose_sum",
     "mdx_trace_kernel",
 ]
-TRACEABLE_KERNELS = ["part_hist", "part_scatter", "seg_hist", "seg_scatter", "rj_join", "grp_count",
+TRACEABLE_KERNELS = ["part_hist", "part_scatter", "seg_hist", "seg_scatter", "rj_join", "cnt_insert",
+                     "cnt_probe", "grp_count",
                      "grp_alloc", "grp_scatter",
                      "tbl_init", "tbl_insert", "probe_chain", "probe_expand", "transpose_sum"]
 
@@ -351,6 +356,40 @@ def mdx_join_probe(table: Table, keys: torch.Tensor, payload: torch.Tensor, offs
                   _dev(status, "status", torch.int32, 1) if status is not None else None,
                   _stream(stream)))
     return ok, ol, orr, out_offsets
+
+
+def mdx_join_count_workspace_bytes(n_build: int, n_probe: int, P: int,
+                                   key_type: int = MDX_KEY_I64) -> int:
+    return _bytes(_count_ws, int(n_build), int(n_probe), int(P), int(key_type))
+
+
+def mdx_join_count(left_keys: torch.Tensor, left_offsets: torch.Tensor, right_keys: torch.Tensor,
+                   right_offsets: torch.Tensor, P: int, *, out_offsets=None, workspace=None,
+                   status=None, stream=None):
+    """Per-partition output counts of the inner join of two partitioned
+    tables (as mdx_join_probe's offsets), without materializing it.
+    Asynchronous; returns out_offsets [P+1] (total at [P])."""
+    nl, nr = left_keys.numel(), right_keys.numel()
+    kt = _key_type(left_keys)
+    if right_keys.dtype != left_keys.dtype:
+        raise TypeError("left and right keys must have the same dtype")
+    dev = left_keys.device
+    made = []
+    if out_offsets is None:
+        out_offsets = torch.empty(P + 1, dtype=torch.int64, device=dev)
+        made.append(out_offsets)
+    if workspace is None:
+        workspace = _workspace(mdx_join_count_workspace_bytes(nl, nr, P, kt), dev)
+        made.append(workspace)
+    _handoff(stream, made)
+    _check(_count(_dev(left_keys, "left_keys"), _dev(left_offsets, "left_offsets", torch.int64, P + 1),
+                  nl, _dev(right_keys, "right_keys"),
+                  _dev(right_offsets, "right_offsets", torch.int64, P + 1), nr, int(P), kt,
+                  _dev(workspace, "workspace"), workspace.numel() * workspace.element_size(),
+                  _dev(out_offsets, "out_offsets", torch.int64, P + 1),
+                  _dev(status, "status", torch.int32, 1) if status is not None else None,
+                  _stream(stream)))
+    return out_offsets
 
 
 # ---- merge ---------------------------------------------------------------------------

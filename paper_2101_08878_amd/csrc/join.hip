@@ -686,6 +686,217 @@ __global__ __launch_bounds__(kBlock) void probe_finalize(int P, ProbeWs w, Probe
     }
 }
 
+// ---- count-only join --------------------------------------------------------------
+// The table of the build side holds, per distinct hash, the number of build
+// rows with that hash (slot value; tbl_init sets it to 0).  Both sides'
+// rows are first counted per workgroup in an LDS map of hashes, so a key
+// repeated millions of times costs one global update per workgroup; rows
+// the map cannot take go to the table one by one.
+constexpr int kCountRows = 8;  // rows per thread loaded together
+
+// Entry of hash h in the LDS map (inserted if there is room within
+// kAggProbe probes), or -1.  ~0 marks an empty entry, so a row whose hash is
+// ~0 is never mapped.
+__device__ __forceinline__ int hmap_insert(uint64_t *mkey, uint64_t h)
+{
+    if (h == ~0ull)
+        return -1;
+    // bits 32-42: the partition takes the low bits, a slot's home the top ones
+    uint32_t i = (uint32_t)(h >> 32) >> (32 - 11);
+    for (int k = 0; k < kAggProbe; ++k) {
+        uint64_t cur = mkey[i];
+        if (cur == ~0ull) {
+            cur = atomicCAS((unsigned long long *)&mkey[i], ~0ull, (unsigned long long)h);
+            if (cur == ~0ull)
+                return (int)i;
+        }
+        if (cur == h)
+            return (int)i;
+        i = (i + 1) & (kAggMap - 1);
+    }
+    return -1;
+}
+
+// value[slot of h] += c in partition p, claiming the slot if h is new.  The
+// half holds at most n_p distinct hashes in its H = n_p + 8 slots.
+__device__ __forceinline__ void slot_add(const TView &v, int64_t o0, int p, uint64_t h,
+                                         uint64_t c)
+{
+    int64_t sb, H;
+    part_slots(v, o0, p, sb, H);
+    const uint64_t t = h >> 63;
+    const uint64_t empty = empty_of_half(t);
+    const int64_t base = sb + (int64_t)t * H;
+    uint64_t i = __umul64hi(h << 1, (uint64_t)H);
+    for (int64_t k = 0; k < H; ++k) {
+        uint64_t *sp = v.slots + 2 * (base + (int64_t)i);
+        uint64_t w = __hip_atomic_load(sp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (w == empty) {
+            uint64_t expect = empty;
+            if (__hip_atomic_compare_exchange_strong(sp, &expect, h, __ATOMIC_RELAXED,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                atomicAdd((unsigned long long *)(sp + 1), (unsigned long long)c);
+                return;
+            }
+            w = expect;
+        }
+        if (w == h) {
+            atomicAdd((unsigned long long *)(sp + 1), (unsigned long long)c);
+            return;
+        }
+        if (++i == (uint64_t)H)
+            i = 0;
+    }
+}
+
+// Rows [r0, r1) of the workgroup's share (kAggRows rows each), kCountRows per
+// thread loaded together; fn(row, hash, partition) for every row in its
+// partition, the others reported.
+template <typename K, typename Fn>
+__device__ __forceinline__ void count_rows(const K *__restrict__ keys, const int64_t *off, int P,
+                                           const Dest &d, int64_t r0, int64_t r1, int32_t *status,
+                                           Fn fn)
+{
+    bool bad = false;
+    for (int64_t b = r0; b < r1; b += (int64_t)kCountRows * kBlock) {
+        K k[kCountRows];
+#pragma unroll
+        for (int j = 0; j < kCountRows; ++j) {
+            const int64_t r = b + (int64_t)j * kBlock + threadIdx.x;
+            k[j] = r < r1 ? __builtin_nontemporal_load(keys + r) : K(0);
+        }
+#pragma unroll
+        for (int j = 0; j < kCountRows; ++j) {
+            const int64_t r = b + (int64_t)j * kBlock + threadIdx.x;
+            if (r < r1) {
+                const uint64_t h = fmix64(key_bits(k[j]));
+                const int p = upper_index(off, 0, P, r);
+                if ((int)part_of(h, d) != p)
+                    bad = true;
+                else
+                    fn(h, p);
+            }
+        }
+    }
+    if (bad)
+        or_status(status, MDX_DEV_BAD_PARTITIONING);
+}
+
+// Block: the sanitized build offsets into the table, the sanitized probe
+// offsets, per-partition counts cleared.
+__global__ __launch_bounds__(kBlock) void cnt_setup(const int64_t *__restrict__ lofs,
+                                                    int64_t n_build,
+                                                    const int64_t *__restrict__ rofs,
+                                                    int64_t n_probe, int64_t *off_tab,
+                                                    int64_t *off_probe, uint64_t *pcount, int P)
+{
+    __shared__ int64_t scratch[kWavesPerBlock];
+    sanitize_offsets(lofs, off_tab, P, n_build, scratch);
+    sanitize_offsets(rofs, off_probe, P, n_probe, scratch);
+    for (int p = threadIdx.x; p < P; p += kBlock)
+        pcount[p] = 0;
+}
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void cnt_insert(const K *__restrict__ keys, TView v,
+                                                     int32_t *status)
+{
+    __shared__ uint64_t mkey[kAggMap];
+    __shared__ uint32_t mcnt[kAggMap];
+    for (int i = threadIdx.x; i < kAggMap; i += kBlock) {
+        mkey[i] = ~0ull;
+        mcnt[i] = 0;
+    }
+    __syncthreads();
+    int64_t o0, r0, r1;
+    agg_rows(v, o0, r0, r1);
+    count_rows(keys, v.off, v.pe, v.d, r0, r1, status, [&](uint64_t h, int p) {
+        const int e = hmap_insert(mkey, h);
+        if (e >= 0)
+            atomicAdd(&mcnt[e], 1u);
+        else
+            slot_add(v, o0, p, h, 1);
+    });
+    __syncthreads();
+    for (int i = threadIdx.x; i < kAggMap; i += kBlock)
+        if (mkey[i] != ~0ull)
+            slot_add(v, o0, (int)part_of(mkey[i], v.d), mkey[i], mcnt[i]);
+}
+
+// Build rows of hash h in partition p (0 when absent).
+__device__ __forceinline__ uint64_t slot_count(const TView &v, int64_t o0, int p, uint64_t h)
+{
+    int64_t sb, H;
+    part_slots(v, o0, p, sb, H);
+    const int64_t s = find_slot(v.slots, sb, H, h);
+    return s >= 0 ? v.slots[2 * s + 1] : 0;
+}
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void cnt_probe(const K *__restrict__ keys,
+                                                    const int64_t *__restrict__ off_probe,
+                                                    TView v, uint64_t *pcount, int32_t *status)
+{
+    extern __shared__ unsigned long long psum[];  // [P]
+    __shared__ uint64_t mkey[kAggMap];
+    __shared__ uint32_t mcnt[kAggMap];
+    const int P = v.pe;
+    for (int i = threadIdx.x; i < kAggMap; i += kBlock) {
+        mkey[i] = ~0ull;
+        mcnt[i] = 0;
+    }
+    for (int p = threadIdx.x; p < P; p += kBlock)
+        psum[p] = 0;
+    __syncthreads();
+    const int64_t o0 = v.off[0];
+    const int64_t n = off_probe[P];
+    const int64_t r0 = off_probe[0] + (int64_t)blockIdx.x * kAggRows;
+    const int64_t r1 = r0 + kAggRows < n ? r0 + kAggRows : n;
+    count_rows(keys, off_probe, P, v.d, r0, r1, status, [&](uint64_t h, int p) {
+        const int e = hmap_insert(mkey, h);
+        if (e >= 0) {
+            atomicAdd(&mcnt[e], 1u);
+        } else {
+            const uint64_t c = slot_count(v, o0, p, h);
+            if (c)
+                atomicAdd(&psum[p], (unsigned long long)c);
+        }
+    });
+    __syncthreads();
+    for (int i = threadIdx.x; i < kAggMap; i += kBlock) {
+        const uint64_t h = mkey[i];
+        if (h != ~0ull) {
+            const int p = (int)part_of(h, v.d);
+            const uint64_t c = slot_count(v, o0, p, h);
+            if (c)
+                atomicAdd(&psum[p], (unsigned long long)(c * mcnt[i]));
+        }
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < P; p += kBlock)
+        if (psum[p])
+            atomicAdd((unsigned long long *)&pcount[p], psum[p]);
+}
+
+// Block: out_offsets = exclusive prefix of the per-partition counts.
+__global__ __launch_bounds__(kBlock) void cnt_finalize(const uint64_t *__restrict__ pcount, int P,
+                                                       int64_t *out_offsets)
+{
+    __shared__ int64_t scratch[kWavesPerBlock];
+    int64_t carry = 0;
+    for (int base = 0; base < P; base += kBlock) {
+        const int p = base + threadIdx.x;
+        const int64_t c = p < P ? (int64_t)pcount[p] : 0;
+        int64_t tot;
+        const int64_t ex = block_excl_scan(c, scratch, &tot);
+        if (p < P)
+            out_offsets[p] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0)
+        out_offsets[P] = carry;
+}
+
 // Workgroups of the grid-stride build and probe kernels: a full device, or
 // fewer when the caller sizes the grid to its rows (max_blocks > 0).
 static int table_grid(int max_blocks)
@@ -744,7 +955,46 @@ hipError_t run_probe_group(const K *pk, const int64_t *pv, const TView &v, int g
     return hipGetLastError();
 }
 
+template <typename K>
+hipError_t run_count(const K *lk, const int64_t *lofs, int64_t n_build, const K *rk,
+                     const int64_t *rofs, int64_t n_probe, const TView &v, int64_t *off_probe,
+                     uint64_t *pcount, int64_t *out_offsets, int32_t *status, hipStream_t s)
+{
+    const int P = v.pe;
+    hipLaunchKernelGGL(cnt_setup, dim3(1), dim3(kBlock), 0, s, lofs, n_build, rofs, n_probe,
+                       (int64_t *)v.off, off_probe, pcount, P);
+    trace_begin("tbl_init", s);
+    hipLaunchKernelGGL(tbl_init, dim3(table_grid(0)), dim3(kBlock), 0, s, v);
+    trace_end("tbl_init", s);
+    if (n_build > 0) {
+        trace_begin("cnt_insert", s);
+        hipLaunchKernelGGL((cnt_insert<K>), dim3((unsigned)((n_build + kAggRows - 1) / kAggRows)),
+                           dim3(kBlock), 0, s, lk, v, status);
+        trace_end("cnt_insert", s);
+    }
+    if (n_probe > 0) {
+        trace_begin("cnt_probe", s);
+        hipLaunchKernelGGL((cnt_probe<K>), dim3((unsigned)((n_probe + kAggRows - 1) / kAggRows)),
+                           dim3(kBlock), (size_t)P * 8, s, rk, off_probe, v, pcount, status);
+        trace_end("cnt_probe", s);
+    }
+    hipLaunchKernelGGL(cnt_finalize, dim3(1), dim3(kBlock), 0, s, pcount, P, out_offsets);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_join_count(const void *lk, const int64_t *lofs, int64_t n_build, const void *rk,
+                             const int64_t *rofs, int64_t n_probe, int key_bytes, const TView &v,
+                             int64_t *off_probe, uint64_t *pcount, int64_t *out_offsets,
+                             int32_t *status, hipStream_t s)
+{
+    if (key_bytes == 8)
+        return run_count<int64_t>((const int64_t *)lk, lofs, n_build, (const int64_t *)rk, rofs,
+                                  n_probe, v, off_probe, pcount, out_offsets, status, s);
+    return run_count<int32_t>((const int32_t *)lk, lofs, n_build, (const int32_t *)rk, rofs,
+                              n_probe, v, off_probe, pcount, out_offsets, status, s);
+}
 
 hipError_t launch_table_setup(const int64_t *off_in, int64_t n, int64_t *off_tab, int32_t *flags,
                               int64_t *bump, int32_t P, hipStream_t s)

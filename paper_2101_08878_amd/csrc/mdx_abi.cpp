@@ -168,10 +168,10 @@ int32_t mdx_trace_kernel(const char *kernel, hipEvent_t *h_starts, hipEvent_t *h
         g_ntrace = 0;
         return MDX_OK;
     }
-    static const char *known[] = {"part_hist", "part_scatter", "tbl_init",
-                                  "tbl_insert", "probe_chain", "probe_expand",
-                                  "seg_hist", "seg_scatter", "rj_join", "grp_count",
-                                  "grp_alloc", "grp_scatter", "transpose_sum"};
+    static const char *known[] = {"part_hist",  "part_scatter", "tbl_init",    "tbl_insert",
+                                  "probe_chain", "probe_expand", "seg_hist",    "seg_scatter",
+                                  "rj_join",    "cnt_insert",   "cnt_probe",   "grp_count",
+                                  "grp_alloc",  "grp_scatter",  "transpose_sum"};
     bool ok = false;
     for (const char *k : known)
         ok |= std::string(k) == kernel;
@@ -489,6 +489,104 @@ int32_t mdx_join_probe(const mdx_table *h_table, const void *d_keys, const int64
                                d_status, 0, stream);
     if (e == hipSuccess)
         e = launch_probe_finalize(P, w, o, nullptr, stream);
+    return e == hipSuccess ? MDX_OK : hip_fail(e, W);
+}
+
+// ---- count-only join ---------------------------------------------------------------
+
+namespace {
+
+// d_ws of mdx_join_count: sanitized build and probe offsets, per-partition
+// counts, then the count table's slots.
+struct CountLayout {
+    int64_t nslots;
+    size_t off_off, offp_off, pcount_off, slots_off, bytes;
+};
+
+CountLayout count_layout(int64_t n_build, int32_t P)
+{
+    CountLayout L;
+    L.nslots = 2 * n_build + 16 * (int64_t)P;
+    size_t o = 0;
+    L.off_off = o;
+    o += align_up((size_t)(P + 1) * 8);
+    L.offp_off = o;
+    o += align_up((size_t)(P + 1) * 8);
+    L.pcount_off = o;
+    o += align_up((size_t)P * 8);
+    L.slots_off = o;
+    o += align_up((size_t)L.nslots * 16);
+    L.bytes = o;
+    return L;
+}
+
+int32_t check_keys(const void *keys, const int64_t *ofs, int64_t n, int32_t kt, const char *W,
+                   const char *side)
+{
+    if (n > 0 && !keys)
+        return fail(MDX_ERR_INVALID, std::string(W) + ": null " + side + " keys with n > 0");
+    if (!aligned(keys, (size_t)kt))
+        return fail(MDX_ERR_INVALID, std::string(W) + ": misaligned " + side + " keys");
+    if (!ofs || !aligned(ofs, 8))
+        return fail(MDX_ERR_INVALID, std::string(W) + ": " + side + " offsets null or misaligned");
+    return MDX_OK;
+}
+
+}  // namespace
+
+int32_t mdx_join_count_workspace_bytes(int64_t n_build, int64_t n_probe, int32_t P,
+                                       int32_t key_type, size_t *h_bytes)
+{
+    g_err.clear();
+    const char *W = "mdx_join_count_workspace_bytes";
+    if (int32_t e = check_sizes(n_build, P, key_type, W))
+        return e;
+    if (int32_t e = check_sizes(n_probe, P, key_type, W))
+        return e;
+    if (!h_bytes)
+        return fail(MDX_ERR_INVALID, std::string(W) + ": h_bytes is null");
+    *h_bytes = count_layout(n_build, P).bytes;
+    return MDX_OK;
+}
+
+int32_t mdx_join_count(const void *d_lkeys, const int64_t *d_lofs, int64_t n_build,
+                       const void *d_rkeys, const int64_t *d_rofs, int64_t n_probe, int32_t P,
+                       int32_t key_type, void *d_ws, size_t ws_bytes, int64_t *d_out_offsets,
+                       int32_t *d_status, hipStream_t stream)
+{
+    g_err.clear();
+    const char *W = "mdx_join_count";
+    if (int32_t e = check_sizes(n_build, P, key_type, W))
+        return e;
+    if (int32_t e = check_sizes(n_probe, P, key_type, W))
+        return e;
+    if (int32_t e = check_keys(d_lkeys, d_lofs, n_build, key_type, W, "build"))
+        return e;
+    if (int32_t e = check_keys(d_rkeys, d_rofs, n_probe, key_type, W, "probe"))
+        return e;
+    if (!d_out_offsets || !aligned(d_out_offsets, 8))
+        return fail(MDX_ERR_INVALID, std::string(W) + ": d_out_offsets null or misaligned");
+    if (!aligned(d_status, 4))
+        return fail(MDX_ERR_INVALID, std::string(W) + ": d_status misaligned");
+    const CountLayout L = count_layout(n_build, P);
+    if (!d_ws || !aligned(d_ws, kAlign))
+        return fail(MDX_ERR_INVALID, std::string(W) + ": workspace null or not 256-byte aligned");
+    if (ws_bytes < L.bytes)
+        return fail(MDX_ERR_WORKSPACE,
+                    std::string(W) + ": workspace needs " + std::to_string(L.bytes) + " bytes");
+    if (overlap(d_ws, ws_bytes, d_out_offsets, (size_t)(P + 1) * 8))
+        return fail(MDX_ERR_INVALID, std::string(W) + ": workspace overlaps d_out_offsets");
+    char *b = (char *)d_ws;
+    TView v = {};
+    v.slots = (uint64_t *)(b + L.slots_off);
+    v.off = (const int64_t *)(b + L.off_off);
+    v.pb = 0;
+    v.pe = P;
+    v.d = make_dest(P);
+    const hipError_t e = launch_join_count(d_lkeys, d_lofs, n_build, d_rkeys, d_rofs, n_probe,
+                                           key_type, v, (int64_t *)(b + L.offp_off),
+                                           (uint64_t *)(b + L.pcount_off), d_out_offsets,
+                                           d_status, stream);
     return e == hipSuccess ? MDX_OK : hip_fail(e, W);
 }
 

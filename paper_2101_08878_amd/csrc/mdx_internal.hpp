@@ -425,6 +425,15 @@ hipError_t launch_probe_group(const void *pkeys, const int64_t *ppay, int key_by
 hipError_t launch_probe_finalize(int32_t P, const ProbeWs &w, const ProbeOut &o,
                                  const int32_t *skip, hipStream_t s);
 
+// Count-only join of two partitioned tables (full views, pb = 0, pe = P):
+// per-partition output counts into out_offsets (exclusive prefix, total at
+// [P]).  v: a table view (off, slots; v.off is written with the sanitized
+// build offsets); off_probe [P+1] and pcount [P] are workspace.
+hipError_t launch_join_count(const void *lk, const int64_t *lofs, int64_t n_build, const void *rk,
+                             const int64_t *rofs, int64_t n_probe, int key_bytes, const TView &v,
+                             int64_t *off_probe, uint64_t *pcount, int64_t *out_offsets,
+                             int32_t *status, hipStream_t s);
+
 // Radix join: plan (the LDS-fit flag from the build sub-buckets, cleared
 // chained scan), join, output offsets.  chunked: a build sub-bucket larger
 // than a table is joined in table-sized chunks (the flag stays set and no

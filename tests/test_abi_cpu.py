@@ -306,6 +306,35 @@ def test_autotune_lookup_reads_cells(tmp_path):
     assert autotune.lookup(8, 2000, str(tmp_path / "missing.json")) == {}
 
 
+def test_join_count_validation():
+    """mdx_join_count's sizing and every check before a launch."""
+    need = mdx.mdx_join_count_workspace_bytes(10**6, 2 * 10**6, 16)
+    assert need % 256 == 0 and need >= 16 * (2 * 10**6 + 16 * 16)
+    assert mdx.mdx_join_count_workspace_bytes(10**6, 10**9, 16) == need  # build side sizes it
+    out = ctypes.c_size_t(0)
+    assert L._count_ws(-1, 10, 4, 8, ctypes.byref(out)) == mdx.MDX_ERR_INVALID
+    assert L._count_ws(10, 10, 0, 8, ctypes.byref(out)) == mdx.MDX_ERR_INVALID
+    assert L._count_ws(10, 10, 4, 2, ctypes.byref(out)) == mdx.MDX_ERR_INVALID
+    need = mdx.mdx_join_count_workspace_bytes(1000, 2000, 4)
+    ws, offs = FAKE + (64 << 30), FAKE + (70 << 30)
+
+    def call(lk=FAKE, lo=FAKE + 4096, nl=1000, rk=FAKE + (1 << 30), ro=FAKE + 8192, nr=2000, P=4,
+             kt=8, w=ws, wb=need, out=offs, st=None):
+        return L._count(lk, lo, nl, rk, ro, nr, P, kt, w, wb, out, st, None)
+
+    assert call(wb=need - 256) == mdx.MDX_ERR_WORKSPACE
+    assert call(lk=None) == mdx.MDX_ERR_INVALID
+    assert call(rk=FAKE + 4) == mdx.MDX_ERR_INVALID            # misaligned int64 keys
+    assert call(lo=None) == mdx.MDX_ERR_INVALID
+    assert call(ro=FAKE + 3) == mdx.MDX_ERR_INVALID
+    assert call(out=None) == mdx.MDX_ERR_INVALID
+    assert call(st=FAKE + 2) == mdx.MDX_ERR_INVALID
+    assert call(w=ws + 64) == mdx.MDX_ERR_INVALID
+    assert call(out=ws + 512) == mdx.MDX_ERR_INVALID           # output inside the workspace
+    assert call(P=0) == mdx.MDX_ERR_INVALID
+    assert call(kt=5) == mdx.MDX_ERR_INVALID
+
+
 def test_merge_workspace_monotone_in_both_sides():
     """A server slot and a batch lane are sized at the largest merge they
     take, which covers every smaller one only if a merge's workspace never

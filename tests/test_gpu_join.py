@@ -124,3 +124,77 @@ def test_table_reuse_across_probes():
         got = dict(key=host(ok), lpay=host(ol), rpay=host(orr), off=host(off),
                    status=int(status.item()), cap=100_000)
         assert_join_equals_oracle(kl, vl, k, v, P, got)
+
+
+# ---- count-only join (mdx_join_count) ----------------------------------------------------
+
+def _count(kl, kr, P, lofs=None, rofs=None, status=None):
+    import paper_2101_08878_amd as mdx
+    pay_l = np.arange(kl.size, dtype=np.int64)
+    pay_r = np.arange(kr.size, dtype=np.int64)
+    if lofs is None:
+        lk, _, lo = mdx.mdx_hash_partition(dev(kl), dev(pay_l), P)
+        rk, _, ro = mdx.mdx_hash_partition(dev(kr), dev(pay_r), P)
+    else:
+        lk, lo, rk, ro = dev(kl), lofs, dev(kr), rofs
+    off = mdx.mdx_join_count(lk, lo, rk, ro, P, status=status)
+    torch.cuda.synchronize()
+    return host(off)
+
+
+@pytest.mark.parametrize("case", ["plain", "zipf", "all_equal", "unique", "int32_negative",
+                                  "empty_left", "empty_right", "both_empty"])
+@pytest.mark.parametrize("P", [1, 7, 64])
+def test_join_count_matches_oracle(case, P):
+    """Per-partition counts equal the oracle's: repeated keys on both sides
+    (Zipf; one key 20000 times), distinct keys, negative int32 keys, empty
+    sides, P = 1, 7 (not a power of two) and 64."""
+    announce(f"join count {case} P={P}")
+    from workloads import zipf_tables
+    if case == "plain":
+        kl, _, kr, _ = uniform_tables(40_000, 50_000, 30_000, seed=21)
+    elif case == "zipf":
+        kl, _, kr, _ = zipf_tables(60_000, 60_000, 1.1, 10_000, seed=22)
+    elif case == "all_equal":
+        kl, kr = np.full(20_000, 5, np.int64), np.concatenate([np.full(300, 5, np.int64),
+                                                              np.arange(6, 4000, dtype=np.int64)])
+    elif case == "unique":
+        kl, _, kr, _ = match_fraction_tables(70_000, 90_000, 0.3, seed=23)
+    else:
+        kl, _, kr, _, _ = edge_tables(case)
+    ref = oracle.join(kl, np.arange(kl.size, dtype=np.int64), kr, np.arange(kr.size, dtype=np.int64),
+                      P=P, materialize=False)
+    off = _count(kl, kr, P)
+    assert off[0] == 0 and off[-1] == ref["total"]
+    assert np.array_equal(np.diff(off), ref["per_part"])
+
+
+def test_join_count_many_partitions_and_large_counts():
+    """P = 4096, and one key with 3E5 copies on each side (9E10 output rows,
+    beyond 32 bits)."""
+    announce("join count P=4096 and a 9e10-row key")
+    kl, _, kr, _ = uniform_tables(200_000, 200_000, 150_000, seed=24)
+    ref = oracle.join(kl, np.arange(kl.size, dtype=np.int64), kr, np.arange(kr.size, dtype=np.int64),
+                      P=4096, materialize=False)
+    assert np.array_equal(np.diff(_count(kl, kr, 4096)), ref["per_part"])
+    kl = np.concatenate([np.full(300_000, -7, np.int64), np.arange(1000, dtype=np.int64)])
+    kr = np.concatenate([np.arange(500, 1500, dtype=np.int64), np.full(300_000, -7, np.int64)])
+    off = _count(kl, kr, 3)
+    ref = oracle.join(kl, np.arange(kl.size, dtype=np.int64), kr, np.arange(kr.size, dtype=np.int64),
+                      P=3, materialize=False)
+    assert np.array_equal(np.diff(off), ref["per_part"]) and off[-1] == 9 * 10**10 + 500
+
+
+def test_join_count_bad_partitioning_is_reported():
+    """Unpartitioned rows with offsets that claim a partitioning: flagged,
+    skipped, nothing faults."""
+    import paper_2101_08878_amd as mdx
+    announce("join count bad partitioning")
+    kl, _, kr, _ = uniform_tables(4_000, 4_000, 1_000, seed=3)
+    P = 4
+    off = torch.tensor([0, 1000, 2000, 3000, 4000], dtype=torch.int64, device="cuda")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    got = _count(kl, kr, P, off, off, status)
+    assert int(status.item()) & mdx.MDX_DEV_BAD_PARTITIONING
+    assert got[-1] <= oracle.join(kl, np.zeros(kl.size, np.int64), kr, np.zeros(kr.size, np.int64),
+                                  materialize=False)["total"]

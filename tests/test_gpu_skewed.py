@@ -68,6 +68,23 @@ def test_skewed_partition_build_count(skewed):
     assert int(host(off)[-1]) == ref["total"] > 10**13
 
 
+def test_skewed_join_count(skewed):
+    """The count-only join (the graded step's count) at full size: exact
+    per-partition counts of the ~5.3E13-row join."""
+    import paper_2101_08878_amd as mdx
+    announce("skewed 5e7 x 5e7: partition + count-only join")
+    kl, vl, kr, vr, ref = skewed
+    P = 16
+    lk, _, lo = mdx.mdx_hash_partition(dev(kl), dev(vl), P)
+    rk, _, ro = mdx.mdx_hash_partition(dev(kr), dev(vr), P)
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    off = mdx.mdx_join_count(lk, lo, rk, ro, P, status=status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    assert np.array_equal(np.diff(host(off)), ref["per_part"])
+    assert int(host(off)[-1]) == ref["total"]
+
+
 def test_skewed_merge_counts(skewed):
     """mdx_merge with a 1-row output: every partition's count still exact,
     overflow reported, nothing written past the capacity."""
