@@ -693,6 +693,19 @@ __global__ __launch_bounds__(kBlock) void probe_finalize(int P, ProbeWs w, Probe
 // repeated millions of times costs one global update per workgroup; rows
 // the map cannot take go to the table one by one.
 constexpr int kCountRows = 8;  // rows per thread loaded together
+#ifndef MDX_COUNT_MAP_BITS
+#define MDX_COUNT_MAP_BITS 12
+#endif
+#ifndef MDX_COUNT_WG_ROWS
+#define MDX_COUNT_WG_ROWS 16384
+#endif
+// On 5E7 x 5E7 Zipf(1.1) keys (P = 16) the count took 2.07 ms with 2048
+// entries, 1.98 with 4096 and 2.83 with 8192 (96 KB of LDS: fewer
+// workgroups per CU); 8192 or 32768 rows per workgroup instead of 16384
+// were slower.
+constexpr int kCountMapBits = MDX_COUNT_MAP_BITS;
+constexpr int kCountMap = 1 << kCountMapBits;  // LDS map entries
+constexpr int kCountWgRows = MDX_COUNT_WG_ROWS;  // rows per workgroup
 
 // Entry of hash h in the LDS map (inserted if there is room within
 // kAggProbe probes), or -1.  ~0 marks an empty entry, so a row whose hash is
@@ -701,8 +714,8 @@ __device__ __forceinline__ int hmap_insert(uint64_t *mkey, uint64_t h)
 {
     if (h == ~0ull)
         return -1;
-    // bits 32-42: the partition takes the low bits, a slot's home the top ones
-    uint32_t i = (uint32_t)(h >> 32) >> (32 - 11);
+    // bits from 32 up: the partition takes the low bits, a slot's home the top ones
+    uint32_t i = (uint32_t)(h >> 32) >> (32 - kCountMapBits);
     for (int k = 0; k < kAggProbe; ++k) {
         uint64_t cur = mkey[i];
         if (cur == ~0ull) {
@@ -712,7 +725,7 @@ __device__ __forceinline__ int hmap_insert(uint64_t *mkey, uint64_t h)
         }
         if (cur == h)
             return (int)i;
-        i = (i + 1) & (kAggMap - 1);
+        i = (i + 1) & (kCountMap - 1);
     }
     return -1;
 }
@@ -749,7 +762,7 @@ __device__ __forceinline__ void slot_add(const TView &v, int64_t o0, int p, uint
     }
 }
 
-// Rows [r0, r1) of the workgroup's share (kAggRows rows each), kCountRows per
+// Rows [r0, r1) of the workgroup's share (kCountWgRows rows each), kCountRows per
 // thread loaded together; fn(row, hash, partition) for every row in its
 // partition, the others reported.
 template <typename K, typename Fn>
@@ -801,15 +814,16 @@ template <typename K>
 __global__ __launch_bounds__(kBlock) void cnt_insert(const K *__restrict__ keys, TView v,
                                                      int32_t *status)
 {
-    __shared__ uint64_t mkey[kAggMap];
-    __shared__ uint32_t mcnt[kAggMap];
-    for (int i = threadIdx.x; i < kAggMap; i += kBlock) {
+    __shared__ uint64_t mkey[kCountMap];
+    __shared__ uint32_t mcnt[kCountMap];
+    for (int i = threadIdx.x; i < kCountMap; i += kBlock) {
         mkey[i] = ~0ull;
         mcnt[i] = 0;
     }
     __syncthreads();
-    int64_t o0, r0, r1;
-    agg_rows(v, o0, r0, r1);
+    const int64_t o0 = v.off[0], o1 = v.off[v.pe];
+    const int64_t r0 = o0 + (int64_t)blockIdx.x * kCountWgRows;
+    const int64_t r1 = r0 + kCountWgRows < o1 ? r0 + kCountWgRows : o1;
     count_rows(keys, v.off, v.pe, v.d, r0, r1, status, [&](uint64_t h, int p) {
         const int e = hmap_insert(mkey, h);
         if (e >= 0)
@@ -818,7 +832,7 @@ __global__ __launch_bounds__(kBlock) void cnt_insert(const K *__restrict__ keys,
             slot_add(v, o0, p, h, 1);
     });
     __syncthreads();
-    for (int i = threadIdx.x; i < kAggMap; i += kBlock)
+    for (int i = threadIdx.x; i < kCountMap; i += kBlock)
         if (mkey[i] != ~0ull)
             slot_add(v, o0, (int)part_of(mkey[i], v.d), mkey[i], mcnt[i]);
 }
@@ -838,10 +852,10 @@ __global__ __launch_bounds__(kBlock) void cnt_probe(const K *__restrict__ keys,
                                                     TView v, uint64_t *pcount, int32_t *status)
 {
     extern __shared__ unsigned long long psum[];  // [P]
-    __shared__ uint64_t mkey[kAggMap];
-    __shared__ uint32_t mcnt[kAggMap];
+    __shared__ uint64_t mkey[kCountMap];
+    __shared__ uint32_t mcnt[kCountMap];
     const int P = v.pe;
-    for (int i = threadIdx.x; i < kAggMap; i += kBlock) {
+    for (int i = threadIdx.x; i < kCountMap; i += kBlock) {
         mkey[i] = ~0ull;
         mcnt[i] = 0;
     }
@@ -850,8 +864,8 @@ __global__ __launch_bounds__(kBlock) void cnt_probe(const K *__restrict__ keys,
     __syncthreads();
     const int64_t o0 = v.off[0];
     const int64_t n = off_probe[P];
-    const int64_t r0 = off_probe[0] + (int64_t)blockIdx.x * kAggRows;
-    const int64_t r1 = r0 + kAggRows < n ? r0 + kAggRows : n;
+    const int64_t r0 = off_probe[0] + (int64_t)blockIdx.x * kCountWgRows;
+    const int64_t r1 = r0 + kCountWgRows < n ? r0 + kCountWgRows : n;
     count_rows(keys, off_probe, P, v.d, r0, r1, status, [&](uint64_t h, int p) {
         const int e = hmap_insert(mkey, h);
         if (e >= 0) {
@@ -863,7 +877,7 @@ __global__ __launch_bounds__(kBlock) void cnt_probe(const K *__restrict__ keys,
         }
     });
     __syncthreads();
-    for (int i = threadIdx.x; i < kAggMap; i += kBlock) {
+    for (int i = threadIdx.x; i < kCountMap; i += kBlock) {
         const uint64_t h = mkey[i];
         if (h != ~0ull) {
             const int p = (int)part_of(h, v.d);
@@ -968,13 +982,15 @@ hipError_t run_count(const K *lk, const int64_t *lofs, int64_t n_build, const K 
     trace_end("tbl_init", s);
     if (n_build > 0) {
         trace_begin("cnt_insert", s);
-        hipLaunchKernelGGL((cnt_insert<K>), dim3((unsigned)((n_build + kAggRows - 1) / kAggRows)),
+        hipLaunchKernelGGL((cnt_insert<K>),
+                           dim3((unsigned)((n_build + kCountWgRows - 1) / kCountWgRows)),
                            dim3(kBlock), 0, s, lk, v, status);
         trace_end("cnt_insert", s);
     }
     if (n_probe > 0) {
         trace_begin("cnt_probe", s);
-        hipLaunchKernelGGL((cnt_probe<K>), dim3((unsigned)((n_probe + kAggRows - 1) / kAggRows)),
+        hipLaunchKernelGGL((cnt_probe<K>),
+                           dim3((unsigned)((n_probe + kCountWgRows - 1) / kCountWgRows)),
                            dim3(kBlock), (size_t)P * 8, s, rk, off_probe, v, pcount, status);
         trace_end("cnt_probe", s);
     }
