@@ -1135,7 +1135,7 @@ FusedMerge fused_merge(const mdx_merge_desc &d, int32_t idx, const Tuned &t)
     take(F.jbase, (size_t)F.S * 8);
     F.bytes = o;
     F.blocks[kTiles] = F.pl.ntiles + F.pr.ntiles;
-    F.blocks[kScan] = 2 * F.nA;
+    F.blocks[kScan] = (2 * F.nA + kWavesPerBlock - 1) / kWavesPerBlock;
     F.blocks[kOffs] = 2;
     F.blocks[kSegPlan] = two ? 2 : 0;
     F.blocks[kSegHist] = two ? F.sl.max_chunks + F.sr.max_chunks : 0;

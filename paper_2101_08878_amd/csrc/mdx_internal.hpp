@@ -178,8 +178,8 @@ size_t seg_rec_bytes();
 void seg_rec(const SegArgs *tables, int key_bytes, int64_t nseg, int shift, int bits, void *dst);
 
 // First pass of M merges of one key width and rows per thread R: `tiles`
-// (both tables' tiles per merge), `scan` (2 D per merge), `offs` (2 per
-// merge).  maxD: the largest destination count; dig: some merge writes
+// (both tables' tiles per merge), `scan` (ceil(2 D / kWavesPerBlock) per
+// merge: a wave per table and destination), `offs` (2 per merge).  maxD: the largest destination count; dig: some merge writes
 // digit bytes.
 hipError_t launch_partition_batch(const void *recs, int M, int key_bytes, int R, int maxD, bool dig,
                                   BatchStage tiles, BatchStage scan, BatchStage offs, hipStream_t s);

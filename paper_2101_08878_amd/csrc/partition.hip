@@ -823,16 +823,37 @@ __global__ __launch_bounds__(kBlock) void part_hist_batch(const PartRec<K> *__re
     hist_tile<K, R>(r.T.t[second], second ? b - r.T.t[0].ntiles : b, r.d, hist);
 }
 
+// One wave per (table, destination) -- merge m owns kWavesPerBlock of them
+// per block, 2 D in all: a batch's tables mostly have few tiles, and a whole
+// block per destination row left most of it idle.  The wave scans its row
+// 64 counts at a time.
 template <typename K>
 __global__ __launch_bounds__(kBlock) void part_scan_batch(const PartRec<K> *__restrict__ B,
                                                           const uint32_t *__restrict__ pre, int M)
 {
     const int m = find_range(pre, M, blockIdx.x);
     const PartRec<K> &r = B[m];
-    const int b = (int)(blockIdx.x - pre[m]), D = r.d.ndest;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int b = (int)(blockIdx.x - pre[m]) * kWavesPerBlock + (int)(threadIdx.x / kWave);
+    const int D = r.d.ndest;
+    if (b >= 2 * D)
+        return;
     const int second = b >= D;
     const PartTable<K> &t = r.T.t[second];
-    scan_tiles_of(t.cnt, t.ntiles, t.totals, second ? b - D : b);
+    const int p = second ? b - D : b;
+    const int64_t ntiles = t.ntiles;
+    int64_t *row = t.cnt + (int64_t)p * ntiles;
+    int64_t carry = 0;
+    for (int64_t base = 0; base < ntiles; base += kWave) {
+        const int64_t i = base + lane;
+        const int64_t v = i < ntiles ? row[i] : 0;
+        const int64_t inc = wave_incl_scan(v, lane);
+        if (i < ntiles)
+            row[i] = carry + inc - v;
+        carry += __shfl(inc, kWave - 1, kWave);
+    }
+    if (lane == 0)
+        t.totals[p] = carry;
 }
 
 template <typename K>
