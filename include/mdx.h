@@ -390,6 +390,9 @@ int32_t mdx_merge_batch(int32_t count, const mdx_merge_desc *h_descs, int32_t la
  * whose replays then need the batch, d_ws and every merge's buffers alive
  * and unchanged.  Runs of one batch must be ordered (they share d_ws).
  * mdx_batch_info reports the waves and kernel launches of one run.
+ * mdx_batch_destroy waits until the last run enqueued outside a capture has
+ * copied the records, then frees them; the caller destroys no batch whose
+ * graph may still be replayed.
  * Errors: MDX_ERR_INVALID for count < 0, a null h_descs with count > 0,
  * bad tuning, a descriptor mdx_merge would reject (the message names the
  * merge); MDX_ERR_WORKSPACE when d_ws is smaller than *h_min_bytes;

@@ -1204,7 +1204,8 @@ struct mdx_batch {
     int device = 0;
     char *d_ws = nullptr;
     size_t image_bytes = 0;
-    char *h_image = nullptr;  // pinned
+    char *h_image = nullptr;   // pinned
+    hipEvent_t copied = nullptr;  // after the last eager run's copy of h_image
     std::vector<BatchUnit> units;
     int32_t waves = 0, launches = 0;
 };
@@ -1430,6 +1431,18 @@ int32_t mdx_batch_run(mdx_batch *batch, hipStream_t stream)
     char *img = batch->d_ws;
     hipError_t e = hipMemcpyAsync(img, batch->h_image, batch->image_bytes, hipMemcpyHostToDevice,
                                   stream);
+    // an eager run's copy reads the pinned image after this call returns:
+    // mdx_batch_destroy waits for it (a captured run's copy belongs to its
+    // graph, which the caller keeps the batch alive for)
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (e == hipSuccess)
+        e = hipStreamIsCapturing(stream, &cap);
+    if (e == hipSuccess && cap == hipStreamCaptureStatusNone) {
+        if (!batch->copied)
+            e = hipEventCreateWithFlags(&batch->copied, hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = hipEventRecord(batch->copied, stream);
+    }
     for (const BatchUnit &u : batch->units) {
         if (e != hipSuccess)
             break;
@@ -1457,8 +1470,15 @@ int32_t mdx_batch_destroy(mdx_batch *batch)
     if (!batch)
         return MDX_OK;
     hipError_t e = hipSuccess;
-    if (batch->h_image)
-        e = hipHostFree(batch->h_image);
+    if (batch->copied) {
+        e = hipEventSynchronize(batch->copied);
+        const hipError_t e2 = hipEventDestroy(batch->copied);
+        e = e == hipSuccess ? e2 : e;
+    }
+    if (batch->h_image) {
+        const hipError_t e2 = hipHostFree(batch->h_image);
+        e = e == hipSuccess ? e2 : e;
+    }
     delete batch;
     return e == hipSuccess ? MDX_OK : hip_fail(e, "mdx_batch_destroy");
 }
