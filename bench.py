@@ -1093,6 +1093,32 @@ def main():
     }
     if args.config == "plain":
         line["us_per_merge"] = round(ms * 1e3, 2)
+    if args.config == "paper":
+        # secondary: the same tables joined as one partition (P = 1: one
+        # 1E8-row table, far beyond any cache), timed after the graded steps
+        off1 = torch.empty(2, dtype=torch.int64, device=dev)
+        ws1 = torch.empty(mdx.mdx_merge_workspace_bytes(nl, nr, 1, key_bytes), dtype=torch.uint8,
+                          device=dev)
+
+        def step1():
+            mdx.mdx_merge(lk, lv, rk, rv, 1, out_capacity=cap, out=out, out_offsets=off1,
+                          workspace=ws1, status=status, stream=stream)
+
+        step1()
+        torch.cuda.synchronize()
+        if int(off1[-1].item()) != total or int(status.item()) != 0:
+            raise SystemExit("P = 1 merge: |J| or status differs")
+        reps = max(2, min(args.steps, 5))
+        e0.record(stream)
+        for _ in range(reps):
+            step1()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms1 = e0.elapsed_time(e1) / reps
+        log(f"secondary, P = 1: {ms1:.3f} ms/step, {(nl + nr) / (ms1 / 1e3):.4g} input rows/s")
+        line["secondary_p1"] = {"P": 1, "ms_per_step": round(ms1, 4), "steps": reps,
+                                "input_rows_per_s": round((nl + nr) / (ms1 / 1e3), 1)}
+        del ws1
     if full_tables is not None:
         del lk, lv, rk, rv, ws, out
         one, allc = cpu_baselines(args.cpu_baseline, args.cpu_sample_scale, full_tables, P)
