@@ -826,7 +826,7 @@ __global__ __launch_bounds__(kBlock) void part_hist_batch(const PartRec<K> *__re
 // One wave per (table, destination) -- merge m owns kWavesPerBlock of them
 // per block, 2 D in all: a batch's tables mostly have few tiles, and a whole
 // block per destination row left most of it idle.  The wave scans its row
-// 64 counts at a time.
+// 64 kScanLane counts at a time, each lane kScanLane consecutive ones.
 template <typename K>
 __global__ __launch_bounds__(kBlock) void part_scan_batch(const PartRec<K> *__restrict__ B,
                                                           const uint32_t *__restrict__ pre, int M)
@@ -843,13 +843,24 @@ __global__ __launch_bounds__(kBlock) void part_scan_batch(const PartRec<K> *__re
     const int p = second ? b - D : b;
     const int64_t ntiles = t.ntiles;
     int64_t *row = t.cnt + (int64_t)p * ntiles;
+    constexpr int kScanLane = 8;
     int64_t carry = 0;
-    for (int64_t base = 0; base < ntiles; base += kWave) {
-        const int64_t i = base + lane;
-        const int64_t v = i < ntiles ? row[i] : 0;
-        const int64_t inc = wave_incl_scan(v, lane);
-        if (i < ntiles)
-            row[i] = carry + inc - v;
+    for (int64_t base = 0; base < ntiles; base += (int64_t)kWave * kScanLane) {
+        const int64_t i0 = base + (int64_t)lane * kScanLane;
+        int64_t v[kScanLane], sum = 0;
+#pragma unroll
+        for (int j = 0; j < kScanLane; ++j) {
+            v[j] = i0 + j < ntiles ? row[i0 + j] : 0;
+            sum += v[j];
+        }
+        const int64_t inc = wave_incl_scan(sum, lane);
+        int64_t run = carry + inc - sum;
+#pragma unroll
+        for (int j = 0; j < kScanLane; ++j) {
+            if (i0 + j < ntiles)
+                row[i0 + j] = run;
+            run += v[j];
+        }
         carry += __shfl(inc, kWave - 1, kWave);
     }
     if (lane == 0)
