@@ -131,8 +131,8 @@ def cpu_baselines(mode, scale, full_tables, P):
     sample of the same generator -- or at full size with mode "full"; (2) the
     same algorithms over all available host cores (per-thread histograms
     with a (destination, block)-major prefix, then one destination per
-    thread joined by sort-merge) at full size.  Capped at 16 threads: the
-    GPU machine gives one GPU's process 16 cores."""
+    thread joined by sort-merge) at full size.  Capped at 16 threads, the
+    host cores a one-GPU process is given there."""
     import oracle
     from workloads import config_inputs
 
@@ -823,9 +823,9 @@ def run_skewed(args):
     wms = e0.elapsed_time(e1) / reps
     wgbs = wrows * 24 / (wms / 1e3) / 1e9
     log(f"window merge: {wms:.3f} ms, {wgbs:.0f} GB/s of output written")
-    # the survey's accounting of the graded step: partition (read + write
-    # 16 B per row), build (16 B read + 16 B table write per left row),
-    # count (8 B key + 16 B slot per right row)
+    # credited bytes of the graded step: partition (read + write 16 B per
+    # row), build (16 B read + 16 B table write per left row), count (8 B
+    # key + 16 B slot per right row)
     alg = (nl + nr) * 2 * 16 + nl * 32 + nr * 24
     achieved = alg / (ms / 1e3) / 1e9
     line = {
