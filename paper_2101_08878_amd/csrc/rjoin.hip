@@ -325,6 +325,89 @@ struct JoinLds {
     int64_t *s_excl, *s_total;
 };
 
+// The common sub-bucket: its build rows fit one table and its probe rows one
+// batch (0 < nb <= kJoinCap, 0 < eR - bR <= kJoinBatch).  A wave's loads
+// complete in the order they were issued, and waiting for one waits for all
+// issued before it; so they are issued in the order they are needed, with
+// no branch around any of them (so that the compiler counts them exactly):
+// the build rows (the inserts wait for these alone), the probe keys (the
+// match), then, once the table is built, the probe payloads (needed only to
+// write the output, so they arrive during the count and the chained scan).
+template <typename K>
+__device__ __forceinline__ void join_one_batch(const K *__restrict__ lk,
+                                               const int64_t *__restrict__ lv, int64_t bL,
+                                               int64_t nb, const K *__restrict__ rk,
+                                               const int64_t *__restrict__ rv, int64_t bR,
+                                               int64_t eR, uint64_t *jstatus, int64_t *jbase,
+                                               int64_t s, const ProbeOut &o, int32_t *status,
+                                               const JoinLds &L)
+{
+    static_assert(kBuildBatch * kJoinThreads >= kJoinCap, "one load batch per table");
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    const uint32_t blast = (uint32_t)nb - 1, plast = (uint32_t)(eR - bR) - 1;
+    K bk[kBuildBatch];
+    int64_t bv[kBuildBatch];
+#pragma unroll
+    for (int j = 0; j < kBuildBatch; ++j) {
+        const uint32_t i = (uint32_t)(j * kJoinThreads + tid);
+        bk[j] = __builtin_nontemporal_load(lk + bL + (i < blast ? i : blast));
+    }
+#pragma unroll
+    for (int j = 0; j < kBuildBatch; ++j) {
+        const uint32_t i = (uint32_t)(j * kJoinThreads + tid);
+        bv[j] = __builtin_nontemporal_load(lv + bL + (i < blast ? i : blast));
+    }
+    K kk[kJoinRows];
+#pragma unroll
+    for (int j = 0; j < kJoinRows; ++j) {
+        const uint32_t r = (uint32_t)(j * kJoinThreads + tid);
+        kk[j] = __builtin_nontemporal_load(rk + bR + (r < plast ? r : plast));
+    }
+    for (int i = tid; i < kJoinHeads; i += kJoinThreads)
+        L.head[i] = kSent;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kBuildBatch; ++j) {
+        const int i = j * kJoinThreads + tid;
+        if (i < nb) {
+            const int64_t k = (int64_t)bk[j];
+            L.tkey[i] = k;
+            L.tp[i] = bv[j];
+            L.tn[i] = (uint16_t)atomicExch(&L.head[bucket_of(k)], (uint32_t)i);
+        }
+    }
+    __syncthreads();
+    int64_t vv[kJoinRows];
+#pragma unroll
+    for (int j = 0; j < kJoinRows; ++j) {
+        const uint32_t r = (uint32_t)(j * kJoinThreads + tid);
+        vv[j] = __builtin_nontemporal_load(rv + bR + (r < plast ? r : plast));
+    }
+
+    uint32_t mf[kJoinRows];
+    match_batch(bR, eR, true, L.tkey, L.tn, L.head, kk, mf);
+    cell_sums(mf, L.cw, lane, wv);
+    __syncthreads();
+    if (wv == 0) {
+        const int64_t total = cell_scan(L.cw, lane);
+        const int64_t ex = lookback(jstatus, s, total, lane, status);
+        if (lane == 0) {
+            *L.s_excl = ex;
+            *L.s_total = total;
+            jbase[s] = ex;
+        }
+    }
+    __syncthreads();
+    const int64_t E = *L.s_excl, total = *L.s_total;
+    if (E + total > o.cap) {
+        if (tid == 0 && total > 0)
+            or_status(status, MDX_DEV_OUTPUT_OVERFLOW);
+    } else if (total > 0) {
+        emit_batch(kk, vv, mf, L.cw, E, L.tkey, L.tp, L.tn, (K *)o.key, o.lpay, o.rpay, lane,
+                   wv);
+    }
+}
+
 // Sub-bucket s of one merge: build rows [bL, bL + nb), probe rows [bR, eR).
 // Publishes its output count to the merge's chained scan (jstatus) and its
 // first output row to jbase[s], then writes its output rows.  With CHUNKED,
@@ -407,18 +490,21 @@ __device__ __forceinline__ void join_sub_bucket(const K *__restrict__ lk,
         return;
     }
 
+    if (nb > 0 && nb <= kJoinCap && nbatch == 1) {
+        join_one_batch<K>(lk, lv, bL, nb, rk, rv, bR, eR, jstatus, jbase, s, o, status, L);
+        return;
+    }
+
+    // Any other sub-bucket (no build rows, no probe rows, or probe rows
+    // beyond one batch).
     const bool any = nb > 0 && nbatch > 0;
-    // Build, with the first probe batch's loads issued before the inserts.
-    if (nbatch > 0)
-        load_batch(rk, rv, bR, eR, kk, vv);
     if (any)
         build_table(lk, lv, bL, nb, L.tkey, L.tp, L.tn, L.head);
 
     // Count every probe row's matches.
     int64_t total = 0;
     for (int64_t b = 0; b < nbatch; ++b) {
-        if (b > 0)
-            load_batch(rk, rv, bR + b * kJoinBatch, eR, kk, vv);
+        load_batch(rk, rv, bR + b * kJoinBatch, eR, kk, vv);
         match_batch(bR + b * kJoinBatch, eR, any, L.tkey, L.tn, L.head, kk, mf);
         cell_sums(mf, L.cw, lane, wv);
         __syncthreads();
