@@ -1393,6 +1393,7 @@ int32_t mdx_batch_create(int32_t count, const mdx_merge_desc *h_descs,
             jr.status = d.d_status;
             jr.P = d.P;
             jr.qbits = f.plan.qbits;
+            jr.by_part = rjoin_by_partition(f.plan.qbits, rjoin_grid(u.total[kSubs])) ? 1 : 0;
             memcpy(B->h_image + u.join_off + j * sizeof(JoinRec), &jr, sizeof(jr));
             for (int st = 0; st < kSteps; ++st)
                 pre[st].push_back(pre[st].back() + (uint32_t)f.blocks[st]);

@@ -246,23 +246,19 @@ constexpr uint64_t kFlagIncl = 2ull << 62;
 constexpr uint64_t kValMask = (1ull << 62) - 1;
 constexpr int64_t kSpinLimit = 1ll << 24;
 
-// Chained scan step for tile `tile` with count `agg`, run by one full wave.
-// Returns the number of output rows of all earlier tiles.  Every tile that
-// was handed out publishes, so the wait below ends; as a guard it gives up
-// after kSpinLimit polls and reports MDX_DEV_SCAN_TIMEOUT.
-
-__device__ inline int64_t lookback(uint64_t *st, int64_t tile, int64_t agg, int lane, int32_t *status)
+// Sum of the values of tiles [0, tile), run by one full wave: walks back
+// from tile - 1, 64 tiles at a time, adding published counts up to the
+// nearest inclusive prefix, and waits while a tile before it is still
+// unpublished.  Every tile that was handed out publishes, so the wait ends;
+// as a guard it gives up after kSpinLimit polls, reports
+// MDX_DEV_SCAN_TIMEOUT and sets *ok = false.
+__device__ inline int64_t prefix_before(const uint64_t *st, int64_t tile, int lane,
+                                        int32_t *status, bool *ok)
 {
-    if (tile == 0) {
-        if (lane == 0)
-            st_agent(st, kFlagIncl | (uint64_t)agg);
-        return 0;
-    }
-    if (lane == 0)
-        st_agent(st + tile, kFlagAgg | (uint64_t)agg);
     int64_t excl = 0;
     int64_t j = tile - 1;
     int64_t polls = 0;
+    *ok = true;
     for (;;) {
         const int64_t idx = j - lane;
         const uint64_t s = idx >= 0 ? ld_agent(st + idx) : kFlagIncl;
@@ -275,6 +271,7 @@ __device__ inline int64_t lookback(uint64_t *st, int64_t tile, int64_t agg, int 
             if (++polls > kSpinLimit) {
                 if (lane == 0)
                     or_status(status, MDX_DEV_SCAN_TIMEOUT);
+                *ok = false;
                 break;
             }
             __builtin_amdgcn_s_sleep(1);
@@ -285,6 +282,22 @@ __device__ inline int64_t lookback(uint64_t *st, int64_t tile, int64_t agg, int 
             break;
         j -= kWave;
     }
+    return excl;
+}
+
+// Chained scan step for tile `tile` with count `agg`, run by one full wave.
+// Returns the number of output rows of all earlier tiles.
+__device__ inline int64_t lookback(uint64_t *st, int64_t tile, int64_t agg, int lane, int32_t *status)
+{
+    if (tile == 0) {
+        if (lane == 0)
+            st_agent(st, kFlagIncl | (uint64_t)agg);
+        return 0;
+    }
+    if (lane == 0)
+        st_agent(st + tile, kFlagAgg | (uint64_t)agg);
+    bool ok;
+    const int64_t excl = prefix_before(st, tile, lane, status, &ok);
     if (lane == 0)
         st_agent(st + tile, kFlagIncl | (uint64_t)(excl + agg));
     return excl;

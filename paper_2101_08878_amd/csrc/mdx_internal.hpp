@@ -464,7 +464,18 @@ struct JoinRec {
     ProbeOut o;
     int32_t *status;
     int32_t P, qbits;
+    int32_t by_part;  // rjoin_by_partition: rows placed by partition cursor
+    int32_t pad;
 };
+
+// Workgroups of a radix-join launch over S sub-buckets.
+int rjoin_grid(int64_t S);
+
+// Whether a radix join places its output rows by partition (a cursor per
+// partition and a chained scan over partitions) rather than by sub-bucket
+// (a chained scan over sub-buckets): when a partition's 2^qbits sub-buckets
+// are many times the G workgroups working at once.
+bool rjoin_by_partition(int qbits, int64_t G);
 
 hipError_t launch_rjoin_batch(const JoinRec *recs, int M, const uint32_t *Spre, uint32_t S,
                               uint32_t *ticket, int key_bytes, hipStream_t s);

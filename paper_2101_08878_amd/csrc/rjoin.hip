@@ -65,6 +65,75 @@ __device__ __forceinline__ int64_t uniform(int64_t x)
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+// ---- output placement ------------------------------------------------------
+// Partition p's output rows form one range, [base(p), base(p+1)); the order
+// of its sub-buckets' rows inside that range is free (row order inside a
+// partition is implementation-defined).  Two ways to place them:
+//  - by sub-bucket: a chained scan over all sub-buckets in ticket order
+//    (pst[s] its status, part[s] its first output row).  A sub-bucket
+//    waits until every sub-bucket ticketed before it has been counted.
+//  - by partition: a sub-bucket takes its rows from its partition's cursor
+//    part[p] with one atomic add (the low kDoneBits count the sub-buckets
+//    counted, the bits above the rows taken), and base(p) is the exclusive
+//    prefix of the partition totals, a chained scan over the P entries of
+//    pst: the last sub-bucket of p to be counted publishes p's total.  A
+//    sub-bucket then waits only while an earlier partition still has
+//    sub-buckets being counted.  The sub-buckets of earlier partitions were
+//    all ticketed before this one, to running workgroups, so the wait ends.
+// By partition pays when partitions hold many more sub-buckets than there
+// are workgroups: then few sub-buckets wait at all (1E8 x 1E8 at P = 1:
+// 13.7 instead of 18.4 us per sub-bucket and workgroup).  With partitions
+// of ~2 workgroups' worth (P = 32), half the sub-buckets in flight wait for
+// the partition before and are all released at once when it completes, and
+// their output writes then contend (21 us per sub-bucket): by sub-bucket.
+struct Place {
+    uint64_t *part;   // by partition: [P] rows taken << kDoneBits | counted;
+                      // by sub-bucket: [S] first output row of each
+    uint64_t *pst;    // [P] or [S]: chained-scan status
+    int32_t qbits;    // 2^qbits sub-buckets per partition (qbits < kDoneBits)
+    int32_t by_part;  // 1: by partition, 0: by sub-bucket
+};
+// A merge has at most 2^22 sub-buckets, so the count of a partition's never
+// carries into its rows; the rows taken are kept modulo 2^41 (a carry out
+// of them is lost), and a partition reaching 2^41 output rows (far beyond
+// any output buffer) is reported as an output overflow.
+constexpr int kDoneBits = 23;
+constexpr uint64_t kDoneMask = (1ull << kDoneBits) - 1;
+constexpr uint64_t kRowsLimit = 1ull << (64 - kDoneBits);
+
+// Wave 0 of a workgroup: the output row of sub-bucket s's first row, for its
+// `total` rows.  (cp, cb): the workgroup's last partition and that
+// partition's base, kept across sub-buckets (cp = -1: none yet).
+__device__ inline int64_t place_rows(const Place &pl, int64_t s, int64_t total, int &cp,
+                                     int64_t &cb, int lane, int32_t *status)
+{
+    if (!pl.by_part) {
+        const int64_t ex = lookback(pl.pst, s, total, lane, status);
+        if (lane == 0)
+            pl.part[s] = (uint64_t)ex;
+        return ex;
+    }
+    const int p = (int)(s >> pl.qbits);
+    uint64_t old = 0;
+    if (lane == 0)
+        old = atomicAdd((unsigned long long *)(pl.part + p), ((uint64_t)total << kDoneBits) + 1);
+    old = __shfl(old, 0, kWave);
+    const uint64_t before = old >> kDoneBits;  // rows of p taken before these
+    if (lane == 0 && ((uint64_t)total >= kRowsLimit || before + (uint64_t)total >= kRowsLimit))
+        or_status(status, MDX_DEV_OUTPUT_OVERFLOW);
+    if (lane == 0 && (old & kDoneMask) + 1 == (1ull << pl.qbits))
+        st_agent(pl.pst + p, kFlagAgg | (before + (uint64_t)total));
+    if (p != cp) {
+        bool ok;
+        cb = prefix_before(pl.pst, p, lane, status, &ok);
+        // p - 1's inclusive prefix is base(p): later look-backs stop there
+        if (ok && p > 0 && lane == 0)
+            st_agent(pl.pst + p - 1, kFlagIncl | (uint64_t)cb);
+        cp = p;
+    }
+    return cb + (int64_t)before;
+}
+
 // chunked: oversized build sub-buckets are joined in chunks (the LDS-fit
 // flag stays 1).
 __global__ __launch_bounds__(kBlock) void rj_plan(const int64_t *__restrict__ subL, int64_t S,
@@ -74,6 +143,7 @@ __global__ __launch_bounds__(kBlock) void rj_plan(const int64_t *__restrict__ su
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < S; s += stride) {
         w.status[s] = 0;
+        w.tile_base[s] = 0;
         over |= (subL[s + 1] - subL[s]) > kJoinCap;
     }
     if (over && !chunked)
@@ -110,8 +180,10 @@ __global__ __launch_bounds__(kBlock) void rj_plan_one(const int64_t *__restrict_
     for (int k = 0; k < kPlanOnePerThread; ++k) {
         const int64_t s = threadIdx.x + (int64_t)k * kBlock;
         over |= s < S && b[k] - a[k] > kJoinCap;
-        if (s < S)
+        if (s < S) {
             w.status[s] = 0;
+            w.tile_base[s] = 0;
+        }
     }
     over = __syncthreads_or(over);
     if (threadIdx.x == 0) {
@@ -338,8 +410,8 @@ __device__ __forceinline__ void join_one_batch(const K *__restrict__ lk,
                                                const int64_t *__restrict__ lv, int64_t bL,
                                                int64_t nb, const K *__restrict__ rk,
                                                const int64_t *__restrict__ rv, int64_t bR,
-                                               int64_t eR, uint64_t *jstatus, int64_t *jbase,
-                                               int64_t s, const ProbeOut &o, int32_t *status,
+                                               int64_t eR, const Place &pl, int64_t s, int &cp,
+                                               int64_t &cb, const ProbeOut &o, int32_t *status,
                                                const JoinLds &L)
 {
     static_assert(kBuildBatch * kJoinThreads >= kJoinCap, "one load batch per table");
@@ -390,11 +462,10 @@ __device__ __forceinline__ void join_one_batch(const K *__restrict__ lk,
     __syncthreads();
     if (wv == 0) {
         const int64_t total = cell_scan(L.cw, lane);
-        const int64_t ex = lookback(jstatus, s, total, lane, status);
+        const int64_t ex = place_rows(pl, s, total, cp, cb, lane, status);
         if (lane == 0) {
             *L.s_excl = ex;
             *L.s_total = total;
-            jbase[s] = ex;
         }
     }
     __syncthreads();
@@ -409,8 +480,8 @@ __device__ __forceinline__ void join_one_batch(const K *__restrict__ lk,
 }
 
 // Sub-bucket s of one merge: build rows [bL, bL + nb), probe rows [bR, eR).
-// Publishes its output count to the merge's chained scan (jstatus) and its
-// first output row to jbase[s], then writes its output rows.  With CHUNKED,
+// Counts its output rows, takes them from its partition (place_rows), then
+// writes them.  With CHUNKED,
 // a build side larger than the table is joined one table-sized chunk at a
 // time (every chunk against every probe row: each pair of rows meets once);
 // otherwise nb <= kJoinCap.
@@ -419,9 +490,9 @@ __device__ __forceinline__ void join_sub_bucket(const K *__restrict__ lk,
                                                 const int64_t *__restrict__ lv, int64_t bL,
                                                 int64_t nb, const K *__restrict__ rk,
                                                 const int64_t *__restrict__ rv, int64_t bR,
-                                                int64_t eR, uint64_t *jstatus, int64_t *jbase,
-                                                int64_t s, const ProbeOut &o, int32_t *status,
-                                                const JoinLds &L)
+                                                int64_t eR, const Place &pl, int64_t s, int &cp,
+                                                int64_t &cb, const ProbeOut &o,
+                                                int32_t *status, const JoinLds &L)
 {
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
     K *out_key = (K *)o.key;
@@ -452,11 +523,9 @@ __device__ __forceinline__ void join_sub_bucket(const K *__restrict__ lk,
             }
         }
         if (wv == 0) {
-            const int64_t ex = lookback(jstatus, s, total, lane, status);
-            if (lane == 0) {
+            const int64_t ex = place_rows(pl, s, total, cp, cb, lane, status);
+            if (lane == 0)
                 *L.s_excl = ex;
-                jbase[s] = ex;
-            }
         }
         __syncthreads();
         const int64_t E = *L.s_excl;
@@ -491,7 +560,7 @@ __device__ __forceinline__ void join_sub_bucket(const K *__restrict__ lk,
     }
 
     if (nb > 0 && nb <= kJoinCap && nbatch == 1) {
-        join_one_batch<K>(lk, lv, bL, nb, rk, rv, bR, eR, jstatus, jbase, s, o, status, L);
+        join_one_batch<K>(lk, lv, bL, nb, rk, rv, bR, eR, pl, s, cp, cb, o, status, L);
         return;
     }
 
@@ -517,13 +586,11 @@ __device__ __forceinline__ void join_sub_bucket(const K *__restrict__ lk,
         total += *L.s_total;
     }
 
-    // Chained scan over sub-buckets.
+    // Output rows from the partition's cursor.
     if (wv == 0) {
-        const int64_t ex = lookback(jstatus, s, total, lane, status);
-        if (lane == 0) {
+        const int64_t ex = place_rows(pl, s, total, cp, cb, lane, status);
+        if (lane == 0)
             *L.s_excl = ex;
-            jbase[s] = ex;
-        }
     }
     __syncthreads();
     const int64_t E = *L.s_excl;
@@ -598,26 +665,29 @@ __global__ __launch_bounds__(kJoinThreads)
 __attribute__((amdgpu_waves_per_eu(kJoinSimdWaves, kJoinSimdWaves))) void rj_join(
     const K *__restrict__ lk, const int64_t *__restrict__ lv, const int64_t *__restrict__ subL,
     const K *__restrict__ rk, const int64_t *__restrict__ rv, const int64_t *__restrict__ subR,
-    RJoinWs w, ProbeOut o, int32_t *status)
+    RJoinWs w, int qbits, int by_part, ProbeOut o, int32_t *status)
 {
     if (!CHUNKED && *w.use == 0)
         return;
     MDX_JOIN_LDS
     const int64_t S = w.S;
+    const Place pl = {(uint64_t *)w.tile_base, w.status, qbits, by_part};
+    int cp = -1;
+    int64_t cb = 0;
     for (;;) {
         const int64_t s = take_ticket(w.ticket, &s_next);
         if (s >= S)
             break;
         const int64_t bL = subL[s], nb = subL[s + 1] - bL;
-        join_sub_bucket<K, CHUNKED>(lk, lv, bL, nb, rk, rv, subR[s], subR[s + 1], w.status,
-                                    w.tile_base, s, o, status, L);
+        join_sub_bucket<K, CHUNKED>(lk, lv, bL, nb, rk, rv, subR[s], subR[s + 1], pl, s, cp, cb,
+                                    o, status, L);
         __syncthreads();  // the table is reused by the next sub-bucket
     }
 }
 
 // Every merge of a batch: tickets run over all merges' sub-buckets (merge m
 // owns tickets [Spre[m], Spre[m+1])), so the workgroups stay busy across
-// merges; each merge has its own chained scan.
+// merges; each merge has its own partition cursors and chained scan.
 template <typename K>
 __global__ __launch_bounds__(kJoinThreads)
 __attribute__((amdgpu_waves_per_eu(kJoinSimdWaves, kJoinSimdWaves))) void rj_join_batch(
@@ -627,6 +697,8 @@ __attribute__((amdgpu_waves_per_eu(kJoinSimdWaves, kJoinSimdWaves))) void rj_joi
     const int64_t total = Spre[M];
     int64_t c0 = 0, c1 = 0;  // tickets of the merge whose record is loaded
     JoinRec r = {};
+    int cp = -1;  // place_rows' cache, per merge
+    int64_t cb = 0;
     for (;;) {
         const int64_t t = take_ticket(ticket, &s_next);
         if (t >= total)
@@ -636,47 +708,77 @@ __attribute__((amdgpu_waves_per_eu(kJoinSimdWaves, kJoinSimdWaves))) void rj_joi
             c0 = Spre[m];
             c1 = Spre[m + 1];
             r = B[m];
+            cp = -1;
         }
         const int64_t s = t - c0;
         const int64_t *subL = r.subL, *subR = r.subR;
         const int64_t bL = subL[s];
+        const Place pl = {(uint64_t *)r.jbase, r.jstatus, r.qbits, r.by_part};
         join_sub_bucket<K, true>((const K *)r.lk, r.lv, bL, subL[s + 1] - bL, (const K *)r.rk,
-                                 r.rv, subR[s], subR[s + 1], r.jstatus, r.jbase, s, r.o, r.status,
-                                 L);
+                                 r.rv, subR[s], subR[s + 1], pl, s, cp, cb, r.o, r.status, L);
         __syncthreads();  // the table is reused by the next sub-bucket
     }
 }
 
-// Block m: clear merge m's chained scan.  Block 0 also resets the ticket.
+// Block m: clear merge m's partition cursors and chained scan.  Block 0
+// also resets the ticket.
 __global__ __launch_bounds__(kBlock) void rj_clear_batch(const JoinRec *__restrict__ B,
                                                          uint32_t *ticket)
 {
     const JoinRec &r = B[blockIdx.x];
-    for (int64_t s = threadIdx.x; s < r.S; s += kBlock)
+    for (int64_t s = threadIdx.x; s < r.S; s += kBlock) {
         r.jstatus[s] = 0;
+        r.jbase[s] = 0;
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0)
         *ticket = 0;
 }
 
-// Block m: merge m's output offsets from its chained scan.
+// offsets[0..P] from the placement, one block: by sub-bucket, the first
+// output row of each partition's first sub-bucket and the scan's total; by
+// partition, the exclusive prefix of the partition totals (the rows each
+// partition's cursor took).
+__device__ inline void offsets_from_place(const uint64_t *part, const uint64_t *pst, int P,
+                                          int qbits, int64_t S, bool by_part, int64_t *offsets)
+{
+    if (!by_part) {
+        const int64_t total = (int64_t)(ld_agent(pst + S - 1) & kValMask);
+        for (int p = threadIdx.x; p <= P; p += kBlock)
+            offsets[p] = p < P ? (int64_t)part[(int64_t)p << qbits] : total;
+        return;
+    }
+    __shared__ int64_t scratch[kWavesPerBlock];
+    int64_t carry = 0;
+    for (int b = 0; b < P; b += kBlock) {
+        const int p = b + threadIdx.x;
+        const int64_t v = p < P ? (int64_t)(ld_agent(part + p) >> kDoneBits) : 0;
+        int64_t all;
+        const int64_t ex = block_excl_scan(v, scratch, &all);
+        if (p < P)
+            offsets[p] = carry + ex;
+        carry += all;
+    }
+    if (threadIdx.x == 0)
+        offsets[P] = carry;
+}
+
+// Block m: merge m's output offsets.
 __global__ __launch_bounds__(kBlock) void rj_finalize_batch(const JoinRec *__restrict__ B)
 {
     const JoinRec &r = B[blockIdx.x];
-    const int64_t total = (int64_t)(ld_agent(r.jstatus + r.S - 1) & kValMask);
-    for (int p = threadIdx.x; p <= r.P; p += kBlock)
-        r.o.offsets[p] = p < r.P ? r.jbase[(int64_t)p << r.qbits] : total;
+    offsets_from_place((const uint64_t *)r.jbase, r.jstatus, r.P, r.qbits, r.S, r.by_part != 0,
+                       r.o.offsets);
 }
 
-// Output offsets of a merge: from the radix join's chained scan when it ran
-// (*w.use), else from the global-table probe's (probe tiles, partition-major).
-__global__ __launch_bounds__(kBlock) void merge_finalize(int P, int qbits, RJoinWs w, ProbeWs pw,
-                                                         bool fallback, ProbeOut o)
+// Output offsets of a merge: from the radix join's partition cursors when it
+// ran (*w.use), else from the global-table probe's chained scan (probe tiles,
+// partition-major).
+__global__ __launch_bounds__(kBlock) void merge_finalize(int P, int qbits, int by_part, RJoinWs w,
+                                                         ProbeWs pw, bool fallback, ProbeOut o)
 {
     if (*w.use != 0) {
-        const int64_t S = w.S;
-        const int64_t total = (int64_t)(ld_agent(w.status + S - 1) & kValMask);
-        for (int p = threadIdx.x; p <= P; p += kBlock)
-            o.offsets[p] = p < P ? w.tile_base[(int64_t)p << qbits] : total;
+        offsets_from_place((const uint64_t *)w.tile_base, w.status, P, qbits, w.S, by_part != 0,
+                           o.offsets);
     } else if (fallback) {
         const int64_t TT = pw.tile_start[P];
         const int64_t total = TT > 0 ? (int64_t)(ld_agent(pw.status + TT - 1) & kValMask) : 0;
@@ -688,6 +790,20 @@ __global__ __launch_bounds__(kBlock) void merge_finalize(int P, int qbits, RJoin
 }
 
 }  // namespace
+
+int rjoin_grid(int64_t S)
+{
+    // kJoinPerCu workgroups per CU (all resident at once), or one per
+    // sub-bucket when there are fewer: a workgroup holds half a CU's LDS,
+    // which other merges' kernels may need meanwhile.
+    const int64_t cus = device_fill_blocks() / 8 > 0 ? device_fill_blocks() / 8 : 1;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(cus * kJoinPerCu, S));
+}
+
+bool rjoin_by_partition(int qbits, int64_t G)
+{
+    return ((int64_t)1 << qbits) >= 8 * G;
+}
 
 hipError_t launch_rjoin_plan(const int64_t *subL, const int64_t *subR, int64_t S,
                              const RJoinWs &w, bool chunked, hipStream_t s)
@@ -707,16 +823,18 @@ hipError_t launch_rjoin_plan(const int64_t *subL, const int64_t *subR, int64_t S
 template <bool CHUNKED>
 void launch_rjoin_kernel(int G, const void *lk, const int64_t *lv, const int64_t *subL,
                          const void *rk, const int64_t *rv, const int64_t *subR, int key_bytes,
-                         const RJoinWs &w, const ProbeOut &o, int32_t *status, hipStream_t s)
+                         const RJoinWs &w, int qbits, const ProbeOut &o, int32_t *status,
+                         hipStream_t s)
 {
+    const int by_part = rjoin_by_partition(qbits, G) ? 1 : 0;
     if (key_bytes == 8)
         hipLaunchKernelGGL((rj_join<int64_t, CHUNKED>), dim3(G), dim3(kJoinThreads), 0, s,
-                           (const int64_t *)lk, lv, subL, (const int64_t *)rk, rv, subR, w, o,
-                           status);
+                           (const int64_t *)lk, lv, subL, (const int64_t *)rk, rv, subR, w, qbits,
+                           by_part, o, status);
     else
         hipLaunchKernelGGL((rj_join<int32_t, CHUNKED>), dim3(G), dim3(kJoinThreads), 0, s,
-                           (const int32_t *)lk, lv, subL, (const int32_t *)rk, rv, subR, w, o,
-                           status);
+                           (const int32_t *)lk, lv, subL, (const int32_t *)rk, rv, subR, w, qbits,
+                           by_part, o, status);
 }
 
 hipError_t launch_rjoin(const void *lk, const int64_t *lv, const int64_t *subL, const void *rk,
@@ -725,17 +843,14 @@ hipError_t launch_rjoin(const void *lk, const int64_t *lv, const int64_t *subL, 
                         bool chunked, hipStream_t s)
 {
     (void)P;
-    (void)qbits;
-    // One workgroup per CU (all resident at once), or one per sub-bucket when
-    // there are fewer: a workgroup holds a CU's LDS, which other merges'
-    // kernels may need meanwhile.
-    const int64_t cus = device_fill_blocks() / 8 > 0 ? device_fill_blocks() / 8 : 1;
-    const int G = (int)std::max<int64_t>(1, std::min<int64_t>(cus * kJoinPerCu, w.S));
+    const int G = rjoin_grid(w.S);
     trace_begin("rj_join", s);
     if (chunked)
-        launch_rjoin_kernel<true>(G, lk, lv, subL, rk, rv, subR, key_bytes, w, o, status, s);
+        launch_rjoin_kernel<true>(G, lk, lv, subL, rk, rv, subR, key_bytes, w, qbits, o, status,
+                                  s);
     else
-        launch_rjoin_kernel<false>(G, lk, lv, subL, rk, rv, subR, key_bytes, w, o, status, s);
+        launch_rjoin_kernel<false>(G, lk, lv, subL, rk, rv, subR, key_bytes, w, qbits, o, status,
+                                   s);
     trace_end("rj_join", s);
     return hipGetLastError();
 }
@@ -746,8 +861,7 @@ hipError_t launch_rjoin_batch(const JoinRec *recs, int M, const uint32_t *Spre, 
     if (M <= 0)
         return hipSuccess;
     hipLaunchKernelGGL(rj_clear_batch, dim3((unsigned)M), dim3(kBlock), 0, s, recs, ticket);
-    const int64_t cus = device_fill_blocks() / 8 > 0 ? device_fill_blocks() / 8 : 1;
-    const int G = (int)std::max<int64_t>(1, std::min<int64_t>(cus * kJoinPerCu, S));
+    const int G = rjoin_grid(S);
     trace_begin("rj_join", s);
     if (key_bytes == 8)
         hipLaunchKernelGGL(rj_join_batch<int64_t>, dim3(G), dim3(kJoinThreads), 0, s, recs, Spre,
@@ -764,8 +878,9 @@ hipError_t launch_merge_finalize(int32_t P, int qbits, const RJoinWs &w, const P
                                  const ProbeOut &o, hipStream_t s)
 {
     const ProbeWs none = {};
-    hipLaunchKernelGGL(merge_finalize, dim3(1), dim3(kBlock), 0, s, P, qbits, w, pw ? *pw : none,
-                       pw != nullptr, o);
+    const int by_part = rjoin_by_partition(qbits, rjoin_grid(w.S)) ? 1 : 0;
+    hipLaunchKernelGGL(merge_finalize, dim3(1), dim3(kBlock), 0, s, P, qbits, by_part, w,
+                       pw ? *pw : none, pw != nullptr, o);
     return hipGetLastError();
 }
 

@@ -160,22 +160,17 @@ def test_merge_capacity_overflow():
     assert got["status"] & mdx.MDX_DEV_OUTPUT_OVERFLOW
 
 
-def test_merge_paper_scale_properties():
-    """1E8 x 1E8, P = 32 (what the benchmark times).
-
-    Left keys are a permutation of [0, 1E8), so a right row matches iff its
-    key is below 1E8, and then exactly once: the output must be exactly the
-    right rows with key < 1E8, each paired with the unique left row holding
-    its key (payload = row index), |J| = 3E7, and partition p's block must
-    hold exactly the output keys with destination p."""
-    announce("merge paper scale 1e8")
-    n = 100_000_000
-    kl, vl, kr, vr = config_inputs("paper")
-    got = run_merge(kl, vl, kr, vr, 32, cap=n)
+def assert_paper_merge(kl, kr, P, got):
+    """Left keys are a permutation of [0, n), so a right row matches iff its
+    key is below n, and then exactly once: the output must be exactly the
+    right rows with key < n, each paired with the unique left row holding
+    its key (payload = row index), and partition p's block must hold exactly
+    the output keys with destination p.  This fixes the output up to the
+    order of rows inside a partition."""
+    n = kl.size
     assert got["status"] == 0
     off = got["off"]
     total = int(off[-1])
-    assert total == 30_000_000
     key, lp, rp = got["key"][:total], got["lpay"][:total], got["rpay"][:total]
     # every output row is a genuine match
     assert np.array_equal(kl[lp], key)
@@ -185,5 +180,30 @@ def test_merge_paper_scale_properties():
     assert hits.size == total
     assert np.array_equal(np.sort(rp), hits)
     # partition blocks
-    dest = np.repeat(np.arange(32), np.diff(off))
-    assert np.array_equal(part_np(key, 32), dest)
+    dest = np.repeat(np.arange(P), np.diff(off))
+    assert np.array_equal(part_np(key, P), dest)
+    return total
+
+
+@pytest.mark.parametrize("P", [1, 2, 3])
+def test_merge_placement_by_partition(P):
+    """1.3E7 x 1.3E7 (the 1E8 workload's generator): at P = 1 and 2 a
+    partition holds 8192 or 4096 sub-buckets, at least 8 per workgroup of the
+    join, so its output rows are placed by partition cursor and a chained scan
+    over partitions; at P = 3 (2048) by the chained scan over sub-buckets."""
+    announce(f"merge placement P={P}")
+    kl, vl, kr, vr = config_inputs("paper", scale=0.13)
+    got = run_merge(kl, vl, kr, vr, P)
+    assert assert_paper_merge(kl, kr, P, got) == round(0.3 * kl.size)
+
+
+@pytest.mark.parametrize("P", [32, 1])
+def test_merge_paper_scale_properties(P):
+    """1E8 x 1E8, P = 32 (what the benchmark times) and P = 1 (its secondary
+    figure, output placed by partition cursor): |J| = 3E7, checked row by
+    row as in assert_paper_merge."""
+    announce(f"merge paper scale 1e8 P={P}")
+    n = 100_000_000
+    kl, vl, kr, vr = config_inputs("paper")
+    got = run_merge(kl, vl, kr, vr, P, cap=n)
+    assert assert_paper_merge(kl, kr, P, got) == 30_000_000
