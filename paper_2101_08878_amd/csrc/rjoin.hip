@@ -9,13 +9,12 @@
 //      heads hold the last row inserted per bucket (LDS atomic exchange), so
 //      equal keys share a chain and repeated keys need nothing special;
 //   2. counts the output rows of all its probe rows (walking each row's
-//      chain), publishes that count to a chained scan over sub-buckets
-//      (decoupled look-back), and receives the output rows of all earlier
-//      sub-buckets;
+//      chain) and takes the output row of its first one (output placement,
+//      below);
 //   3. writes (key, left payload, right payload) rows.  When the probe rows
-//      fit one batch (8192 rows) they stay in registers between 2 and 3;
+//      fit one batch (4096 rows) they stay in registers between 2 and 3;
 //      otherwise they are read and looked up again.
-// Sub-buckets are numbered partition-major, so partition p's output is the
+// Sub-buckets are numbered partition-major, and partition p's output is the
 // contiguous range [out_off[p], out_off[p+1]).  Global memory is only
 // streamed: the random accesses of the join all hit LDS.  The partition
 // already sent each key to its sub-bucket by fmix64, so inside a sub-bucket a
@@ -23,10 +22,11 @@
 // compared directly: fmix64 (six 32-bit multiplies, quarter-rate
 // instructions) is not computed again here.
 //
-// Latency hiding with one workgroup per CU: the first probe batch is loaded
-// while the build rows are inserted, and the hash chains of a thread's probe
-// rows are walked four at a time without branches, so that their LDS reads
-// are in flight together.
+// Latency hiding: two workgroups per CU, one running while the other waits
+// on the dependent steps of its sub-bucket; inside a sub-bucket the loads
+// are issued in the order they are needed (join_one_batch), and the hash
+// chains of a thread's probe rows are walked four at a time without
+// branches, so that their LDS reads are in flight together.
 #include <algorithm>
 
 #include "mdx.h"

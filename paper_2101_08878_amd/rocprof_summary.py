@@ -43,17 +43,32 @@ KERNEL_FILES = {
 SHARED_FILES = ("mdx_device.hpp", "mdx_internal.hpp")
 
 
+_CODE_TOKENS = re.compile(r'"(?:\\.|[^"\\])*"|\'(?:\\.|[^\'\\])*\'|//[^\n]*|/\*.*?\*/|\s+', re.S)
+
+
+def code_of(text: str) -> str:
+    """C/C++ source without its comments, whitespace runs collapsed to one
+    space (string and character literals kept as they are)."""
+    def keep(m):
+        t = m.group(0)
+        if t.startswith("//") or t.startswith("/*"):
+            return " "
+        return " " if t.isspace() else t
+    return re.sub(r"\s+", " ", _CODE_TOKENS.sub(keep, text)).strip()
+
+
 def kernel_sources_hash(kernel: str | None = None) -> str:
-    """Hash of the sources a kernel is built from (its own file and the
-    shared device headers; every HIP/C++ source when the kernel is not
-    known): counter figures taken on other sources no longer describe it."""
+    """Hash of the code a kernel is built from (its own file and the shared
+    device headers; every HIP/C++ source when the kernel is not known),
+    comments and layout aside: counter figures taken on other code no longer
+    describe it."""
     csrc = os.path.join(HERE, "csrc")
     own = KERNEL_FILES.get(kernel or "")
     files = sorted((own,) + SHARED_FILES) if own else sorted(os.listdir(csrc))
     h = hashlib.sha256()
     for f in files:
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(f.encode() + fh.read())
+        with open(os.path.join(csrc, f), encoding="utf-8") as fh:
+            h.update((f + "\n" + code_of(fh.read())).encode())
     return h.hexdigest()[:16]
 
 
