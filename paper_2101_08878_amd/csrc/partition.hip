@@ -5,7 +5,8 @@
 // destination p's rows are packed, in input order, into [off[p], off[p+1]).
 //
 // Three passes over tiles of T = kBlock * R rows (512 x 8 = 4096):
-//   part_hist       keys only: per-tile counts per destination (LDS atomics)
+//   part_hist       keys only: per-tile counts per destination (LDS atomics;
+//                   a wave's ballots when there are at most 4 destinations)
 //   part_scan_tiles per destination, exclusive prefix over tiles (in place)
 //   part_offsets    exclusive prefix over destinations -> off[0..P]
 //   part_scatter    keys + payloads: rank rows inside the tile with wave
@@ -70,8 +71,13 @@ __device__ __forceinline__ PartTable<K> pick(const PartPair<K> &T, bool second)
     return r;
 }
 
-// Counts of tile `tile` of table tb per destination into tb.cnt.
-template <typename K, int R>
+// Histograms of at most this many destinations count by ballot: a whole
+// wave's LDS atomics on a few addresses serialize.
+constexpr int kFewDest = 4;
+
+// Counts of tile `tile` of table tb per destination into tb.cnt.  FEW: the
+// destinations may be few enough to count by ballot.
+template <typename K, int R, bool FEW>
 __device__ __forceinline__ void hist_tile(const PartTable<K> &tb, int64_t tile, const Dest &d,
                                           uint32_t *hist)
 {
@@ -80,6 +86,18 @@ __device__ __forceinline__ void hist_tile(const PartTable<K> &tb, int64_t tile, 
     for (int p = tid; p < P; p += kBlock)
         hist[p] = 0;
     const int64_t row0 = tile * (int64_t)(kBlock * R);
+    const bool few = FEW && P <= kFewDest;
+    uint32_t wc[kFewDest] = {};  // with few destinations: the wave's counts
+    auto count = [&](bool valid, uint32_t p) {
+        if (few) {
+#pragma unroll
+            for (int q = 0; q < kFewDest; ++q)
+                if (q < P)
+                    wc[q] += (uint32_t)__popcll(ballot(valid && p == (uint32_t)q));
+        } else if (valid) {
+            atomicAdd(&hist[p], 1u);
+        }
+    };
     // Keys are read 16 bytes per lane when the column is 16-byte aligned
     // (the counts do not depend on which thread reads which row).
     constexpr int V = 16 / (int)sizeof(K);  // keys per 16-byte load
@@ -107,8 +125,7 @@ __device__ __forceinline__ void hist_tile(const PartTable<K> &tb, int64_t tile, 
             const int64_t r = row0 + ((int64_t)j * kBlock + tid) * V;
 #pragma unroll
             for (int v = 0; v < V; ++v)
-                if (r + v < tb.n)
-                    atomicAdd(&hist[dest_of(fmix64(key_bits(k[j * V + v])), d)], 1u);
+                count(r + v < tb.n, dest_of(fmix64(key_bits(k[j * V + v])), d));
         }
     } else {
         K k[R];
@@ -121,16 +138,21 @@ __device__ __forceinline__ void hist_tile(const PartTable<K> &tb, int64_t tile, 
 #pragma unroll
         for (int c = 0; c < R; ++c) {
             const int64_t r = row0 + (int64_t)c * kBlock + tid;
-            if (r < tb.n)
-                atomicAdd(&hist[dest_of(fmix64(key_bits(k[c])), d)], 1u);
+            count(r < tb.n, dest_of(fmix64(key_bits(k[c])), d));
         }
+    }
+    if (few && (tid & (kWave - 1)) == 0) {
+#pragma unroll
+        for (int q = 0; q < kFewDest; ++q)
+            if (q < P && wc[q] != 0)
+                atomicAdd(&hist[q], wc[q]);
     }
     __syncthreads();
     for (int p = tid; p < P; p += kBlock)
         tb.cnt[(int64_t)p * tb.ntiles + tile] = hist[p];
 }
 
-template <typename K, int R>
+template <typename K, int R, bool FEW>
 __global__ __launch_bounds__(kBlock) void part_hist(PartPair<K> T, Dest d)
 {
     extern __shared__ uint32_t hist[];
@@ -138,7 +160,7 @@ __global__ __launch_bounds__(kBlock) void part_hist(PartPair<K> T, Dest d)
     // lines, which then fill in one L2
     const int64_t g = tile_of_block(blockIdx.x, gridDim.x);
     const bool second = g >= T.t[0].ntiles;
-    hist_tile<K, R>(pick(T, second), second ? g - T.t[0].ntiles : g, d, hist);
+    hist_tile<K, R, FEW>(pick(T, second), second ? g - T.t[0].ntiles : g, d, hist);
 }
 
 // Block p: exclusive prefix of cnt[p][0..ntiles) in place, total to totals[p].
@@ -705,8 +727,12 @@ hipError_t run_partition(const PartArgs *tables, int ntables, int32_t P, int sbi
     const int64_t tiles = T.t[0].ntiles + T.t[1].ntiles;
     if (tiles > 0) {
         trace_begin("part_hist", s);
-        hipLaunchKernelGGL((part_hist<K, R>), dim3((unsigned)tiles), dim3(kBlock),
-                           (size_t)D * sizeof(uint32_t), s, T, d);
+        if (D <= kFewDest)
+            hipLaunchKernelGGL((part_hist<K, R, true>), dim3((unsigned)tiles), dim3(kBlock),
+                               (size_t)D * sizeof(uint32_t), s, T, d);
+        else
+            hipLaunchKernelGGL((part_hist<K, R, false>), dim3((unsigned)tiles), dim3(kBlock),
+                               (size_t)D * sizeof(uint32_t), s, T, d);
         trace_end("part_hist", s);
     }
     hipLaunchKernelGGL(part_scan_tiles, dim3((unsigned)(D * ntables)), dim3(kBlock), 0, s,
@@ -820,7 +846,7 @@ __global__ __launch_bounds__(kBlock) void part_hist_batch(const PartRec<K> *__re
     const PartRec<K> &r = B[m];
     const int64_t b = (int64_t)(g - pre[m]);
     const int second = b >= r.T.t[0].ntiles;
-    hist_tile<K, R>(r.T.t[second], second ? b - r.T.t[0].ntiles : b, r.d, hist);
+    hist_tile<K, R, true>(r.T.t[second], second ? b - r.T.t[0].ntiles : b, r.d, hist);
 }
 
 // One wave per (table, destination) -- merge m owns kWavesPerBlock of them
