@@ -117,7 +117,7 @@ def test_partition_key_column_not_16_byte_aligned(dtype, shift):
     assert base.data_ptr() % 16 == 0
     kd = base[skip:]
     assert kd.data_ptr() % 16 != 0
-    for P in [7, 32]:
+    for P in [3, 7, 32]:  # 3: the few-destination histogram on the per-row path
         ko, vo, off = mdx.mdx_hash_partition(kd, torch.from_numpy(pay).to("cuda"), P)
         torch.cuda.synchronize()
         want = oracle.hash_partition(keys[skip:], pay, P)
