@@ -41,6 +41,19 @@ def test_partition_ragged_matches_oracle(P, dtype):
     _assert_same(keys, np.arange(N_RAGGED, dtype=np.int64), P)
 
 
+@pytest.mark.parametrize("P", [1, 2, 4])
+@pytest.mark.parametrize("dtype", [np.int64, np.int32])
+def test_partition_few_destinations_many_tiles(P, dtype):
+    """At most 4 destinations the histogram counts by wave ballots: 1E6 rows
+    (245 tiles and a ragged tail) byte-exact against the oracle."""
+    announce(f"partition few destinations P={P} dtype={np.dtype(dtype).name}")
+    n = 1_000_000
+    info = np.iinfo(dtype)
+    keys = np.random.default_rng(100 + P).integers(info.min, info.max, n, dtype=np.int64,
+                                                  endpoint=True).astype(dtype)
+    _assert_same(keys, np.arange(n, dtype=np.int64), P)
+
+
 @pytest.mark.parametrize("n", [0, 1, 63, 64, 65, 4095, 4096, 4097])
 def test_partition_small_sizes(n):
     announce(f"partition n={n}")
