@@ -369,7 +369,7 @@ int32_t mdx_merge_batch(int32_t count, const mdx_merge_desc *h_descs, int32_t la
  * few keys repeat very many times; mdx_merge handles such inputs better.
  *
  * Tuning (h_tuning: NULL, or one entry per merge): `fill` is the average
- * build rows of a sub-bucket as a fraction of an LDS table (0: 0.8; else in
+ * build rows of a sub-bucket as a fraction of an LDS table (0: 0.9; else in
  * [0.05, 1]); `fanout` caps the first pass's destinations (0: 128; else in
  * [1, 4096]); `part_rows` picks the first pass's rows per thread, 2 or 8
  * (0: by destinations; 8 needs at most 256 destinations, else 2 is used);

@@ -40,7 +40,7 @@ BUCKETS = [(1_000, 4_000), (4_000, 16_000), (16_000, 64_000), (64_000, 256_000),
 FILLS = (0.5, 0.65, 0.8, 0.9)
 FANOUTS = (32, 64, 128, 256)
 PART_ROWS = (2, 8)
-DEFAULT = {"fill": 0.8, "fanout": 128, "part_rows": 8}
+DEFAULT = {"fill": 0.9, "fanout": 128, "part_rows": 8}
 
 _cache: dict = {}
 

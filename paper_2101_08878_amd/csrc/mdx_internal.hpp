@@ -193,19 +193,22 @@ hipError_t launch_seg_batch(const void *recs, int M, int key_bytes, int maxbits,
 // Sub-bucket s of S = P 2^qbits holds build rows [subL[s], subL[s+1]) and
 // probe rows [subR[s], subR[s+1]); partition p owns sub-buckets
 // [p 2^qbits, (p+1) 2^qbits).
-// Two 512-thread workgroups per CU, each with a 76 KB table in LDS: the time
+// Two 512-thread workgroups per CU, each with a 77 KB table in LDS: the time
 // of a sub-bucket is mostly the latency of its dependent steps (ticket,
 // offsets, row loads, chained scan), and a second workgroup on the CU runs
 // while the first waits.  (One workgroup with a 152 KB table for twice the
-// rows, and so half the sub-buckets, was 10% slower at 1E8 x 1E8.)
+// rows, and so half the sub-buckets, was 10% slower at 1E8 x 1E8.)  The
+// table holds 3456 rows under 4096 chain heads: sub-buckets average 0.9 of
+// it (so 1E8 rows in 32 partitions still make 32768 sub-buckets), and
+// chains average under 0.8 rows (3840 rows under 2048 heads was 7% slower).
 #ifndef MDX_JOIN_PER_CU
 #define MDX_JOIN_PER_CU 2
 #endif
 #ifndef MDX_JOIN_CAP
-#define MDX_JOIN_CAP 3840
+#define MDX_JOIN_CAP 3456
 #endif
 #ifndef MDX_JOIN_HEADS
-#define MDX_JOIN_HEADS 2048
+#define MDX_JOIN_HEADS 4096
 #endif
 #ifndef MDX_JOIN_ROWS
 #define MDX_JOIN_ROWS 8
@@ -217,8 +220,12 @@ constexpr int kJoinHeads = MDX_JOIN_HEADS;  // chain heads per LDS table
 constexpr int kJoinRows = MDX_JOIN_ROWS;    // probe rows per thread per batch
 constexpr int kJoinBatch = kJoinThreads * kJoinRows;
 // Sub-buckets are sized for this fraction of a table on average (the larger
-// side's rows): the largest of thousands stays far below the cap.
-constexpr double kJoinFill = 0.8;
+// side's rows): the largest of thousands stays below the cap (at ~3100 rows
+// the cap is six standard deviations of a sub-bucket's size away).
+#ifndef MDX_JOIN_FILL
+#define MDX_JOIN_FILL 0.9
+#endif
+constexpr double kJoinFill = MDX_JOIN_FILL;
 
 // One chained-scan tile per sub-bucket.
 struct RJoinLayout {
