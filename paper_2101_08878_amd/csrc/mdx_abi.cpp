@@ -608,11 +608,13 @@ struct MergePlan {
 };
 
 // fill: average rows of the larger side per sub-bucket, as a fraction of a
-// table; fanout: the first pass's largest number of destinations.
-MergePlan merge_plan(int64_t nL, int64_t nR, int32_t P, double fill = kJoinFill, int fanout = 128)
+// table of `cap` rows (the join's table: the fused batch's holds more rows);
+// fanout: the first pass's largest number of destinations.
+MergePlan merge_plan(int64_t nL, int64_t nR, int32_t P, double fill = kJoinFill, int fanout = 128,
+                     int cap = kJoinCap)
 {
     MergePlan m;
-    const double per = fill * kJoinCap;
+    const double per = fill * cap;
     const double want = (double)std::max(nL, nR) / ((double)P * per);
     m.qbits = want <= 1.0 ? 0 : ceil_log2((int64_t)(want + 0.999999));
     // keep the sub-bucket count bounded; oversized sub-buckets fall back to
@@ -1092,7 +1094,7 @@ FusedMerge fused_merge(const mdx_merge_desc &d, int32_t idx, const Tuned &t)
     FusedMerge F;
     F.idx = idx;
     F.kt = d.key_type;
-    F.plan = merge_plan(d.n_left, d.n_right, d.P, t.fill, t.fanout);
+    F.plan = merge_plan(d.n_left, d.n_right, d.P, t.fill, t.fanout, kBatchJoinCap);
     F.nA = (int64_t)d.P << F.plan.q1bits;
     F.S = (int64_t)d.P << F.plan.qbits;
     const int deflt = part_rows_per_thread((int32_t)F.nA);

@@ -197,10 +197,13 @@ hipError_t launch_seg_batch(const void *recs, int M, int key_bytes, int maxbits,
 // of a sub-bucket is mostly the latency of its dependent steps (ticket,
 // offsets, row loads, chained scan), and a second workgroup on the CU runs
 // while the first waits.  (One workgroup with a 152 KB table for twice the
-// rows, and so half the sub-buckets, was 10% slower at 1E8 x 1E8.)  The
-// table holds 3456 rows under 4096 chain heads: sub-buckets average 0.9 of
-// it (so 1E8 rows in 32 partitions still make 32768 sub-buckets), and
+// rows, and so half the sub-buckets, was 10% slower at 1E8 x 1E8.)  A
+// merge's table holds 3456 rows under 4096 chain heads: sub-buckets average
+// 0.9 of it (so 1E8 rows in 32 partitions still make 32768 sub-buckets), and
 // chains average under 0.8 rows (3840 rows under 2048 heads was 7% slower).
+// The fused batch's join keeps 3840 rows under 2048 heads: its mid-size
+// merges (1E4 to 1E6 rows) gain more from 10% larger sub-buckets (fewer of
+// them) than from shorter chains.
 #ifndef MDX_JOIN_PER_CU
 #define MDX_JOIN_PER_CU 2
 #endif
@@ -210,13 +213,27 @@ hipError_t launch_seg_batch(const void *recs, int M, int key_bytes, int maxbits,
 #ifndef MDX_JOIN_HEADS
 #define MDX_JOIN_HEADS 4096
 #endif
+#ifndef MDX_BATCH_JOIN_CAP
+#define MDX_BATCH_JOIN_CAP 3840
+#endif
+#ifndef MDX_BATCH_JOIN_HEADS
+#define MDX_BATCH_JOIN_HEADS 2048
+#endif
 #ifndef MDX_JOIN_ROWS
 #define MDX_JOIN_ROWS 8
 #endif
 constexpr int kJoinPerCu = MDX_JOIN_PER_CU;
 constexpr int kJoinThreads = 512;
-constexpr int kJoinCap = MDX_JOIN_CAP;      // build rows per LDS table
-constexpr int kJoinHeads = MDX_JOIN_HEADS;  // chain heads per LDS table
+// Geometry of a join workgroup's LDS table: build rows, chain heads.
+template <int CAP, int HEADS>
+struct JoinGeo {
+    static constexpr int cap = CAP;
+    static constexpr int heads = HEADS;
+};
+using MergeJoin = JoinGeo<MDX_JOIN_CAP, MDX_JOIN_HEADS>;             // rj_join
+using BatchJoin = JoinGeo<MDX_BATCH_JOIN_CAP, MDX_BATCH_JOIN_HEADS>;  // rj_join_batch
+constexpr int kJoinCap = MergeJoin::cap;       // build rows per table of a merge
+constexpr int kBatchJoinCap = BatchJoin::cap;  // ... of the fused batch
 constexpr int kJoinRows = MDX_JOIN_ROWS;    // probe rows per thread per batch
 constexpr int kJoinBatch = kJoinThreads * kJoinRows;
 // Sub-buckets are sized for this fraction of a table on average (the larger

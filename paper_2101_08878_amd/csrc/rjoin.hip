@@ -35,26 +35,33 @@
 namespace mdx {
 namespace {
 
-// Chains end at the sentinel row kSent (one slot past the table), whose link
-// points to itself.
-constexpr uint32_t kSent = kJoinCap;
 constexpr int kJoinWaves = kJoinThreads / kWave;
 constexpr int kBuildBatch = 8;  // build rows per thread loaded together
 constexpr int kCells = kJoinRows * kJoinWaves;  // (row step, wave) partial sums
 constexpr int kCellsPerLane = kCells / kWave;
 static_assert(kCells % kWave == 0, "one wave scans the partial sums");
-static_assert(kSent <= 0xffffu, "chain links are 16-bit");
 constexpr int kWalk = 4;  // probe rows whose chains are walked together
 static_assert(kJoinRows % kWalk == 0, "walk groups tile the thread's rows");
 
+// A table of geometry G (G::cap build rows, G::heads chain heads).  Chains
+// end at the sentinel row `sent` (one slot past the table), whose link
+// points to itself.
+template <class G>
+struct Tab {
+    static constexpr uint32_t sent = G::cap;
+    static constexpr int log_heads = __builtin_ctz(G::heads);
+    static_assert(G::cap <= 0xffff, "chain links are 16-bit");
+    static_assert((G::heads & (G::heads - 1)) == 0, "power-of-two heads");
+    static_assert(kBuildBatch * kJoinThreads >= G::cap, "one load batch per table");
+};
+
 // Chain of a key inside its sub-bucket: multiplicative (Fibonacci) hashing
 // of the key's two 32-bit halves folded together.
+template <class G>
 __device__ __forceinline__ uint32_t bucket_of(int64_t key)
 {
-    static_assert((kJoinHeads & (kJoinHeads - 1)) == 0, "power-of-two heads");
-    constexpr int kLog = __builtin_ctz(kJoinHeads);
     const uint32_t x = (uint32_t)key ^ (uint32_t)((uint64_t)key >> 32);
-    return (x * 0x9E3779B1u) >> (32 - kLog);
+    return (x * 0x9E3779B1u) >> (32 - Tab<G>::log_heads);
 }
 
 // Values every lane of the workgroup holds alike, in scalar registers.
@@ -216,16 +223,17 @@ __device__ __forceinline__ void load_batch(const K *__restrict__ rk, const int64
     }
 }
 
-// Per row: the number of matches (high 16 bits; at most kJoinCap) and the
+// Per row: the number of matches (high 16 bits; at most G::cap) and the
 // first matching build row in chain order (low 16 bits; meaningful when the
 // count is not 0).  The chains of kWalk rows are walked together without
 // branches: a finished chain sits on the sentinel row, whose link points to
 // itself, so every step issues all kWalk rows' LDS reads at once.
-template <typename K>
+template <class G, typename K>
 __device__ __forceinline__ void match_batch(int64_t rb, int64_t re, bool any, const int64_t *tkey,
                                             const uint16_t *tn, const uint32_t *head, const K *kk,
                                             uint32_t *mf)
 {
+    constexpr uint32_t kSent = Tab<G>::sent;
     const int64_t left = re - rb;
     const uint32_t n = any ? (uint32_t)(left < kJoinBatch ? left : kJoinBatch) : 0u;
 #pragma unroll
@@ -239,7 +247,7 @@ __device__ __forceinline__ void match_batch(int64_t rb, int64_t re, bool any, co
             const uint32_t r = (uint32_t)(j * kJoinThreads) + threadIdx.x;
             mf[j] = 0;
             h[i] = (int64_t)kk[j];
-            e[i] = r < n ? head[bucket_of(h[i])] : kSent;
+            e[i] = r < n ? head[bucket_of<G>(h[i])] : kSent;
             live |= e[i] != kSent;
         }
         while (ballot(live)) {
@@ -309,12 +317,13 @@ __device__ __forceinline__ int64_t cell_scan(int64_t *cw, int lane)
 
 // Write the output rows of the batch held in registers; base = output row of
 // the batch's first match; cw holds the exclusive cell prefixes.
-template <typename K>
+template <class G, typename K>
 __device__ __forceinline__ void emit_batch(const K *kk, const int64_t *vv, const uint32_t *mf,
                                            const int64_t *cw, int64_t base, const int64_t *tkey,
                                            const int64_t *tp, const uint16_t *tn, K *out_key,
                                            int64_t *out_l, int64_t *out_r, int lane, int wv)
 {
+    constexpr uint32_t kSent = Tab<G>::sent;
 #pragma unroll
     for (int j = 0; j < kJoinRows; ++j) {
         const uint32_t cnt = mf[j] >> 16, fst = mf[j] & 0xffffu;
@@ -324,7 +333,7 @@ __device__ __forceinline__ void emit_batch(const K *kk, const int64_t *vv, const
         const int64_t before =
             many ? wave_incl_scan((int64_t)cnt, lane) - (int64_t)cnt : (int64_t)mbcnt(one);
         // the wave's first output row of this step: a scalar base; lanes add
-        // a 32-bit offset (a step of a wave has at most 64 kJoinCap rows)
+        // a 32-bit offset (a step of a wave has at most 64 G::cap rows)
         const int64_t wb = uniform(base + cw[j * kJoinWaves + wv]);
         K *ok = out_key + wb;
         int64_t *ol = out_l + wb, *orr = out_r + wb;
@@ -347,18 +356,18 @@ __device__ __forceinline__ void emit_batch(const K *kk, const int64_t *vv, const
     }
 }
 
-// Insert build rows [b0, b0 + n) (0 < n <= kJoinCap) into the LDS table,
+// Insert build rows [b0, b0 + n) (0 < n <= G::cap) into the LDS table,
 // kBuildBatch rows per thread at a time.  Rows past n load the last row (no
 // branch per load) and are not inserted.
-template <typename K>
+template <class G, typename K>
 __device__ __forceinline__ void build_table(const K *__restrict__ lk,
                                             const int64_t *__restrict__ lv, int64_t b0, int64_t n,
                                             int64_t *tkey, int64_t *tp, uint16_t *tn,
                                             uint32_t *head)
 {
     const int tid = threadIdx.x;
-    for (int i = tid; i < kJoinHeads; i += kJoinThreads)
-        head[i] = kSent;
+    for (int i = tid; i < G::heads; i += kJoinThreads)
+        head[i] = Tab<G>::sent;
     __syncthreads();
     const K *kb = lk + b0;
     const int64_t *vb = lv + b0;
@@ -380,7 +389,7 @@ __device__ __forceinline__ void build_table(const K *__restrict__ lk,
                 const int64_t k = (int64_t)bk[j];
                 tkey[i] = k;
                 tp[i] = bv[j];
-                tn[i] = (uint16_t)atomicExch(&head[bucket_of(k)], (uint32_t)i);
+                tn[i] = (uint16_t)atomicExch(&head[bucket_of<G>(k)], (uint32_t)i);
             }
         }
     }
@@ -389,23 +398,23 @@ __device__ __forceinline__ void build_table(const K *__restrict__ lk,
 
 // The LDS of a join workgroup.
 struct JoinLds {
-    int64_t *tkey;  // [kJoinCap + 1] key of build row i
-    int64_t *tp;    // [kJoinCap] payload of build row i
-    uint16_t *tn;   // [kJoinCap + 1] next row in i's chain
-    uint32_t *head; // [kJoinHeads] last row inserted per bucket
+    int64_t *tkey;  // [G::cap + 1] key of build row i
+    int64_t *tp;    // [G::cap] payload of build row i
+    uint16_t *tn;   // [G::cap + 1] next row in i's chain
+    uint32_t *head; // [G::heads] last row inserted per bucket
     int64_t *cw;    // [kCells]
     int64_t *s_excl, *s_total;
 };
 
 // The common sub-bucket: its build rows fit one table and its probe rows one
-// batch (0 < nb <= kJoinCap, 0 < eR - bR <= kJoinBatch).  A wave's loads
+// batch (0 < nb <= G::cap, 0 < eR - bR <= kJoinBatch).  A wave's loads
 // complete in the order they were issued, and waiting for one waits for all
 // issued before it; so they are issued in the order they are needed, with
 // no branch around any of them (so that the compiler counts them exactly):
 // the build rows (the inserts wait for these alone), the probe keys (the
 // match), then, once the table is built, the probe payloads (needed only to
 // write the output, so they arrive during the count and the chained scan).
-template <typename K>
+template <class G, typename K>
 __device__ __forceinline__ void join_one_batch(const K *__restrict__ lk,
                                                const int64_t *__restrict__ lv, int64_t bL,
                                                int64_t nb, const K *__restrict__ rk,
@@ -414,7 +423,6 @@ __device__ __forceinline__ void join_one_batch(const K *__restrict__ lk,
                                                int64_t &cb, const ProbeOut &o, int32_t *status,
                                                const JoinLds &L)
 {
-    static_assert(kBuildBatch * kJoinThreads >= kJoinCap, "one load batch per table");
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
     const uint32_t blast = (uint32_t)nb - 1, plast = (uint32_t)(eR - bR) - 1;
     K bk[kBuildBatch];
@@ -435,8 +443,8 @@ __device__ __forceinline__ void join_one_batch(const K *__restrict__ lk,
         const uint32_t r = (uint32_t)(j * kJoinThreads + tid);
         kk[j] = __builtin_nontemporal_load(rk + bR + (r < plast ? r : plast));
     }
-    for (int i = tid; i < kJoinHeads; i += kJoinThreads)
-        L.head[i] = kSent;
+    for (int i = tid; i < G::heads; i += kJoinThreads)
+        L.head[i] = Tab<G>::sent;
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kBuildBatch; ++j) {
@@ -445,7 +453,7 @@ __device__ __forceinline__ void join_one_batch(const K *__restrict__ lk,
             const int64_t k = (int64_t)bk[j];
             L.tkey[i] = k;
             L.tp[i] = bv[j];
-            L.tn[i] = (uint16_t)atomicExch(&L.head[bucket_of(k)], (uint32_t)i);
+            L.tn[i] = (uint16_t)atomicExch(&L.head[bucket_of<G>(k)], (uint32_t)i);
         }
     }
     __syncthreads();
@@ -457,7 +465,7 @@ __device__ __forceinline__ void join_one_batch(const K *__restrict__ lk,
     }
 
     uint32_t mf[kJoinRows];
-    match_batch(bR, eR, true, L.tkey, L.tn, L.head, kk, mf);
+    match_batch<G>(bR, eR, true, L.tkey, L.tn, L.head, kk, mf);
     cell_sums(mf, L.cw, lane, wv);
     __syncthreads();
     if (wv == 0) {
@@ -474,8 +482,8 @@ __device__ __forceinline__ void join_one_batch(const K *__restrict__ lk,
         if (tid == 0 && total > 0)
             or_status(status, MDX_DEV_OUTPUT_OVERFLOW);
     } else if (total > 0) {
-        emit_batch(kk, vv, mf, L.cw, E, L.tkey, L.tp, L.tn, (K *)o.key, o.lpay, o.rpay, lane,
-                   wv);
+        emit_batch<G>(kk, vv, mf, L.cw, E, L.tkey, L.tp, L.tn, (K *)o.key, o.lpay, o.rpay, lane,
+                      wv);
     }
 }
 
@@ -484,8 +492,8 @@ __device__ __forceinline__ void join_one_batch(const K *__restrict__ lk,
 // writes them.  With CHUNKED,
 // a build side larger than the table is joined one table-sized chunk at a
 // time (every chunk against every probe row: each pair of rows meets once);
-// otherwise nb <= kJoinCap.
-template <typename K, bool CHUNKED>
+// otherwise nb <= G::cap.
+template <class G, typename K, bool CHUNKED>
 __device__ __forceinline__ void join_sub_bucket(const K *__restrict__ lk,
                                                 const int64_t *__restrict__ lv, int64_t bL,
                                                 int64_t nb, const K *__restrict__ rk,
@@ -501,16 +509,17 @@ __device__ __forceinline__ void join_sub_bucket(const K *__restrict__ lk,
     int64_t vv[kJoinRows];
     uint32_t mf[kJoinRows];
 
-    if (CHUNKED && nb > kJoinCap && nbatch > 0) {
-        const int64_t nch = (nb + kJoinCap - 1) / kJoinCap;
+    constexpr int64_t kCap = G::cap;
+    if (CHUNKED && nb > kCap && nbatch > 0) {
+        const int64_t nch = (nb + kCap - 1) / kCap;
         int64_t total = 0;
         for (int64_t c = 0; c < nch; ++c) {
-            const int64_t c0 = c * kJoinCap;
-            build_table(lk, lv, bL + c0, nb - c0 < kJoinCap ? nb - c0 : (int64_t)kJoinCap, L.tkey,
-                        L.tp, L.tn, L.head);
+            const int64_t c0 = c * kCap;
+            build_table<G>(lk, lv, bL + c0, nb - c0 < kCap ? nb - c0 : kCap, L.tkey, L.tp, L.tn,
+                           L.head);
             for (int64_t b = 0; b < nbatch; ++b) {
                 load_batch(rk, rv, bR + b * kJoinBatch, eR, kk, vv);
-                match_batch(bR + b * kJoinBatch, eR, true, L.tkey, L.tn, L.head, kk, mf);
+                match_batch<G>(bR + b * kJoinBatch, eR, true, L.tkey, L.tn, L.head, kk, mf);
                 cell_sums(mf, L.cw, lane, wv);
                 __syncthreads();
                 if (wv == 0) {
@@ -536,12 +545,12 @@ __device__ __forceinline__ void join_sub_bucket(const K *__restrict__ lk,
         }
         int64_t run = E;
         for (int64_t c = 0; c < nch && total > 0; ++c) {
-            const int64_t c0 = c * kJoinCap;
-            build_table(lk, lv, bL + c0, nb - c0 < kJoinCap ? nb - c0 : (int64_t)kJoinCap, L.tkey,
-                        L.tp, L.tn, L.head);
+            const int64_t c0 = c * kCap;
+            build_table<G>(lk, lv, bL + c0, nb - c0 < kCap ? nb - c0 : kCap, L.tkey, L.tp, L.tn,
+                           L.head);
             for (int64_t b = 0; b < nbatch; ++b) {
                 load_batch(rk, rv, bR + b * kJoinBatch, eR, kk, vv);
-                match_batch(bR + b * kJoinBatch, eR, true, L.tkey, L.tn, L.head, kk, mf);
+                match_batch<G>(bR + b * kJoinBatch, eR, true, L.tkey, L.tn, L.head, kk, mf);
                 cell_sums(mf, L.cw, lane, wv);
                 __syncthreads();
                 if (wv == 0) {
@@ -550,8 +559,8 @@ __device__ __forceinline__ void join_sub_bucket(const K *__restrict__ lk,
                         *L.s_total = all;
                 }
                 __syncthreads();
-                emit_batch(kk, vv, mf, L.cw, run, L.tkey, L.tp, L.tn, out_key, o.lpay, o.rpay, lane,
-                           wv);
+                emit_batch<G>(kk, vv, mf, L.cw, run, L.tkey, L.tp, L.tn, out_key, o.lpay, o.rpay,
+                              lane, wv);
                 run += *L.s_total;
                 __syncthreads();  // cw, s_total and the table are reused
             }
@@ -559,8 +568,8 @@ __device__ __forceinline__ void join_sub_bucket(const K *__restrict__ lk,
         return;
     }
 
-    if (nb > 0 && nb <= kJoinCap && nbatch == 1) {
-        join_one_batch<K>(lk, lv, bL, nb, rk, rv, bR, eR, pl, s, cp, cb, o, status, L);
+    if (nb > 0 && nb <= kCap && nbatch == 1) {
+        join_one_batch<G, K>(lk, lv, bL, nb, rk, rv, bR, eR, pl, s, cp, cb, o, status, L);
         return;
     }
 
@@ -568,13 +577,13 @@ __device__ __forceinline__ void join_sub_bucket(const K *__restrict__ lk,
     // beyond one batch).
     const bool any = nb > 0 && nbatch > 0;
     if (any)
-        build_table(lk, lv, bL, nb, L.tkey, L.tp, L.tn, L.head);
+        build_table<G>(lk, lv, bL, nb, L.tkey, L.tp, L.tn, L.head);
 
     // Count every probe row's matches.
     int64_t total = 0;
     for (int64_t b = 0; b < nbatch; ++b) {
         load_batch(rk, rv, bR + b * kJoinBatch, eR, kk, vv);
-        match_batch(bR + b * kJoinBatch, eR, any, L.tkey, L.tn, L.head, kk, mf);
+        match_batch<G>(bR + b * kJoinBatch, eR, any, L.tkey, L.tn, L.head, kk, mf);
         cell_sums(mf, L.cw, lane, wv);
         __syncthreads();
         if (wv == 0) {
@@ -604,12 +613,13 @@ __device__ __forceinline__ void join_sub_bucket(const K *__restrict__ lk,
             if (wv == 0)
                 cell_scan(L.cw, lane);
             __syncthreads();
-            emit_batch(kk, vv, mf, L.cw, E, L.tkey, L.tp, L.tn, out_key, o.lpay, o.rpay, lane, wv);
+            emit_batch<G>(kk, vv, mf, L.cw, E, L.tkey, L.tp, L.tn, out_key, o.lpay, o.rpay, lane,
+                          wv);
         } else {
             int64_t run = E;
             for (int64_t b = 0; b < nbatch; ++b) {
                 load_batch(rk, rv, bR + b * kJoinBatch, eR, kk, vv);
-                match_batch(bR + b * kJoinBatch, eR, any, L.tkey, L.tn, L.head, kk, mf);
+                match_batch<G>(bR + b * kJoinBatch, eR, any, L.tkey, L.tn, L.head, kk, mf);
                 cell_sums(mf, L.cw, lane, wv);
                 __syncthreads();
                 if (wv == 0) {
@@ -618,8 +628,8 @@ __device__ __forceinline__ void join_sub_bucket(const K *__restrict__ lk,
                         *L.s_total = all;
                 }
                 __syncthreads();
-                emit_batch(kk, vv, mf, L.cw, run, L.tkey, L.tp, L.tn, out_key, o.lpay, o.rpay, lane,
-                           wv);
+                emit_batch<G>(kk, vv, mf, L.cw, run, L.tkey, L.tp, L.tn, out_key, o.lpay, o.rpay,
+                              lane, wv);
                 run += *L.s_total;
                 __syncthreads();  // cw and s_total are reused by the next batch
             }
@@ -634,17 +644,17 @@ constexpr int kJoinSimdWaves = kJoinPerCu * kJoinThreads / (4 * kWave);
 // Sub-buckets are taken strictly in ticket order, just before each is
 // started: a ticket taken ahead of time would make later sub-buckets wait
 // for it in the chained scan.
-#define MDX_JOIN_LDS                                                                       \
-    __shared__ int64_t tkey[kJoinCap + 1];                                                 \
-    __shared__ int64_t tp[kJoinCap];                                                       \
-    __shared__ uint16_t tn[kJoinCap + 1];                                                  \
-    __shared__ uint32_t head[kJoinHeads];                                                  \
+#define MDX_JOIN_LDS(G)                                                                    \
+    __shared__ int64_t tkey[G::cap + 1];                                                   \
+    __shared__ int64_t tp[G::cap];                                                         \
+    __shared__ uint16_t tn[G::cap + 1];                                                    \
+    __shared__ uint32_t head[G::heads];                                                    \
     __shared__ int64_t cw[kCells];                                                         \
     __shared__ int64_t s_next, s_excl, s_total;                                            \
     const JoinLds L = {tkey, tp, tn, head, cw, &s_excl, &s_total};                         \
     if (threadIdx.x == 0) {                                                                \
-        tkey[kSent] = 0;                                                                   \
-        tn[kSent] = (uint16_t)kSent;                                                       \
+        tkey[G::cap] = 0;                                                                  \
+        tn[G::cap] = (uint16_t)G::cap;                                                     \
     }
 
 // Next ticket, the same on every lane.
@@ -669,7 +679,7 @@ __attribute__((amdgpu_waves_per_eu(kJoinSimdWaves, kJoinSimdWaves))) void rj_joi
 {
     if (!CHUNKED && *w.use == 0)
         return;
-    MDX_JOIN_LDS
+    MDX_JOIN_LDS(MergeJoin)
     const int64_t S = w.S;
     const Place pl = {(uint64_t *)w.tile_base, w.status, qbits, by_part};
     int cp = -1;
@@ -679,8 +689,8 @@ __attribute__((amdgpu_waves_per_eu(kJoinSimdWaves, kJoinSimdWaves))) void rj_joi
         if (s >= S)
             break;
         const int64_t bL = subL[s], nb = subL[s + 1] - bL;
-        join_sub_bucket<K, CHUNKED>(lk, lv, bL, nb, rk, rv, subR[s], subR[s + 1], pl, s, cp, cb,
-                                    o, status, L);
+        join_sub_bucket<MergeJoin, K, CHUNKED>(lk, lv, bL, nb, rk, rv, subR[s], subR[s + 1], pl,
+                                               s, cp, cb, o, status, L);
         __syncthreads();  // the table is reused by the next sub-bucket
     }
 }
@@ -693,7 +703,7 @@ __global__ __launch_bounds__(kJoinThreads)
 __attribute__((amdgpu_waves_per_eu(kJoinSimdWaves, kJoinSimdWaves))) void rj_join_batch(
     const JoinRec *__restrict__ B, const uint32_t *__restrict__ Spre, int M, uint32_t *ticket)
 {
-    MDX_JOIN_LDS
+    MDX_JOIN_LDS(BatchJoin)
     const int64_t total = Spre[M];
     int64_t c0 = 0, c1 = 0;  // tickets of the merge whose record is loaded
     JoinRec r = {};
@@ -714,7 +724,7 @@ __attribute__((amdgpu_waves_per_eu(kJoinSimdWaves, kJoinSimdWaves))) void rj_joi
         const int64_t *subL = r.subL, *subR = r.subR;
         const int64_t bL = subL[s];
         const Place pl = {(uint64_t *)r.jbase, r.jstatus, r.qbits, r.by_part};
-        join_sub_bucket<K, true>((const K *)r.lk, r.lv, bL, subL[s + 1] - bL, (const K *)r.rk,
+        join_sub_bucket<BatchJoin, K, true>((const K *)r.lk, r.lv, bL, subL[s + 1] - bL, (const K *)r.rk,
                                  r.rv, subR[s], subR[s + 1], pl, s, cp, cb, r.o, r.status, L);
         __syncthreads();  // the table is reused by the next sub-bucket
     }
