@@ -200,10 +200,11 @@ hipError_t launch_seg_batch(const void *recs, int M, int key_bytes, int maxbits,
 // rows, and so half the sub-buckets, was 10% slower at 1E8 x 1E8.)  A
 // merge's table holds 3456 rows under 4096 chain heads: sub-buckets average
 // 0.9 of it (so 1E8 rows in 32 partitions still make 32768 sub-buckets), and
-// chains average under 0.8 rows (3840 rows under 2048 heads was 7% slower).
-// The fused batch's join keeps 3840 rows under 2048 heads: its mid-size
-// merges (1E4 to 1E6 rows) gain more from 10% larger sub-buckets (fewer of
-// them) than from shorter chains.
+// chains average under 0.8 rows (3840 rows under 2048 heads was 7% slower),
+// so a thread walks the chains of two probe rows at a time (four: 2%
+// slower).  The fused batch's join keeps 3840 rows under 2048 heads and
+// walks four chains at a time: its mid-size merges (1E4 to 1E6 rows) gain
+// more from 10% larger sub-buckets (fewer of them) than from shorter chains.
 #ifndef MDX_JOIN_PER_CU
 #define MDX_JOIN_PER_CU 2
 #endif
@@ -224,14 +225,16 @@ hipError_t launch_seg_batch(const void *recs, int M, int key_bytes, int maxbits,
 #endif
 constexpr int kJoinPerCu = MDX_JOIN_PER_CU;
 constexpr int kJoinThreads = 512;
-// Geometry of a join workgroup's LDS table: build rows, chain heads.
-template <int CAP, int HEADS>
+// Geometry of a join workgroup's LDS table: build rows, chain heads, and
+// the probe rows of a thread whose chains are walked together.
+template <int CAP, int HEADS, int WALK>
 struct JoinGeo {
     static constexpr int cap = CAP;
     static constexpr int heads = HEADS;
+    static constexpr int walk = WALK;
 };
-using MergeJoin = JoinGeo<MDX_JOIN_CAP, MDX_JOIN_HEADS>;             // rj_join
-using BatchJoin = JoinGeo<MDX_BATCH_JOIN_CAP, MDX_BATCH_JOIN_HEADS>;  // rj_join_batch
+using MergeJoin = JoinGeo<MDX_JOIN_CAP, MDX_JOIN_HEADS, 2>;             // rj_join
+using BatchJoin = JoinGeo<MDX_BATCH_JOIN_CAP, MDX_BATCH_JOIN_HEADS, 4>;  // rj_join_batch
 constexpr int kJoinCap = MergeJoin::cap;       // build rows per table of a merge
 constexpr int kBatchJoinCap = BatchJoin::cap;  // ... of the fused batch
 constexpr int kJoinRows = MDX_JOIN_ROWS;    // probe rows per thread per batch

@@ -40,8 +40,6 @@ constexpr int kBuildBatch = 8;  // build rows per thread loaded together
 constexpr int kCells = kJoinRows * kJoinWaves;  // (row step, wave) partial sums
 constexpr int kCellsPerLane = kCells / kWave;
 static_assert(kCells % kWave == 0, "one wave scans the partial sums");
-constexpr int kWalk = 4;  // probe rows whose chains are walked together
-static_assert(kJoinRows % kWalk == 0, "walk groups tile the thread's rows");
 
 // A table of geometry G (G::cap build rows, G::heads chain heads).  Chains
 // end at the sentinel row `sent` (one slot past the table), whose link
@@ -53,6 +51,7 @@ struct Tab {
     static_assert(G::cap <= 0xffff, "chain links are 16-bit");
     static_assert((G::heads & (G::heads - 1)) == 0, "power-of-two heads");
     static_assert(kBuildBatch * kJoinThreads >= G::cap, "one load batch per table");
+    static_assert(kJoinRows % G::walk == 0, "walk groups tile the thread's rows");
 };
 
 // Chain of a key inside its sub-bucket: multiplicative (Fibonacci) hashing
@@ -225,15 +224,16 @@ __device__ __forceinline__ void load_batch(const K *__restrict__ rk, const int64
 
 // Per row: the number of matches (high 16 bits; at most G::cap) and the
 // first matching build row in chain order (low 16 bits; meaningful when the
-// count is not 0).  The chains of kWalk rows are walked together without
+// count is not 0).  The chains of G::walk rows are walked together without
 // branches: a finished chain sits on the sentinel row, whose link points to
-// itself, so every step issues all kWalk rows' LDS reads at once.
+// itself, so every step issues all G::walk rows' LDS reads at once.
 template <class G, typename K>
 __device__ __forceinline__ void match_batch(int64_t rb, int64_t re, bool any, const int64_t *tkey,
                                             const uint16_t *tn, const uint32_t *head, const K *kk,
                                             uint32_t *mf)
 {
     constexpr uint32_t kSent = Tab<G>::sent;
+    constexpr int kWalk = G::walk;
     const int64_t left = re - rb;
     const uint32_t n = any ? (uint32_t)(left < kJoinBatch ? left : kJoinBatch) : 0u;
 #pragma unroll
