@@ -185,6 +185,26 @@ def test_fused_batch_overflow_and_chunks():
     _check(items[1:], jobs[1:])
 
 
+def test_fused_batch_one_key_at_table_size():
+    """Merges whose build side is one key repeated b times, around the fused
+    batch's LDS table (3840 rows) and twice it: at most one table the
+    sub-bucket is joined at once, beyond it in table-sized chunks."""
+    import paper_2101_08878_amd as mdx
+    announce("fused batch one key at table size")
+    items = []
+    for b in [3839, 3840, 3841, 7680, 7681]:
+        kl = np.full(b, 9, np.int64)
+        kr = np.concatenate([np.full(2, 9, np.int64), np.arange(20, 900, dtype=np.int64)])
+        items.append((kl, np.arange(b, dtype=np.int64), kr, np.arange(kr.size, dtype=np.int64),
+                      2))
+    jobs = _jobs(items)
+    fb = mdx.FusedBatch(jobs)
+    fb.run()
+    torch.cuda.synchronize()
+    _check(items, jobs)
+    fb.close()
+
+
 def test_fused_batch_graph_replays():
     """The batch captured into a graph (the plan's copy to the device and
     every launch); three replays with eager clearing in between, each checked

@@ -132,6 +132,25 @@ def test_merge_fallback_for_oversized_sub_bucket():
     assert_join_equals_oracle(kl, vl, kr, vr, 4, got)
 
 
+@pytest.mark.parametrize("b", [3455, 3456, 3457, 3840, 3841])
+@pytest.mark.parametrize("P", [1, 4])
+def test_merge_one_key_at_table_size(b, P):
+    """A build side of one key repeated b times, so one sub-bucket of b rows:
+    at most 3456 (a merge's LDS table, and then the build side fits one
+    table, so the global-table kernels are not even launched) it is joined
+    in LDS, beyond it the device takes the global-table join.  The probe
+    side has 3 matching rows and 500 misses."""
+    announce(f"merge one key x {b}, P={P}")
+    rng = np.random.default_rng(b + P)
+    kl = np.full(b, 7, np.int64)
+    kr = np.concatenate([np.full(3, 7, np.int64), rng.integers(100, 300, 500)])
+    kr = kr[rng.permutation(kr.size)]
+    vl, vr = np.arange(kl.size, dtype=np.int64), np.arange(kr.size, dtype=np.int64)
+    total = oracle.join(kl, vl, kr, vr, materialize=False)["total"]
+    got = run_merge(kl, vl, kr, vr, P, cap=total)
+    assert_join_equals_oracle(kl, vl, kr, vr, P, got)
+
+
 def test_merge_skewed_reduced():
     announce("merge zipf reduced")
     kl, vl, kr, vr = zipf_tables(15_000, 15_000, 1.1, 10_000, seed=0)
